@@ -1,0 +1,156 @@
+/*
+ * lanczos_topk.h -- C ABI of the MI355X (gfx950) Top-K sparse symmetric
+ * eigensolver: Lanczos with full reorthogonalisation, a Jacobi eigensolve of
+ * the tridiagonal matrix and the Ritz-vector product.
+ *
+ * Method: Sgherzi, Parravicini, Santambrogio, "A Mixed Precision, Multi-GPU
+ * Design for Large-scale Top-K Sparse Eigenproblems" (2022).
+ *   Sec. II, Algorithm 1   Lanczos iteration (SpMV, alpha, three-term update,
+ *                          orthogonalisation, beta, normalisation)
+ *   Sec. II (2nd phase)    Jacobi on the tridiagonal T, Ritz vectors V*S
+ *   Sec. I                 Top-K = the K eigenvalues largest in modulus
+ *   Sec. II-A              storage vs. computation precision (FDF)
+ *   Sec. IV-D              accuracy metrics: L2 residual, pairwise angle
+ *
+ * Conventions shared by every entry point:
+ *   - Return value is an lz_status code; it is the only error channel.
+ *   - Argument errors are detected before anything is enqueued.
+ *   - Device pointers are HIP device allocations owned by the caller; the
+ *     library never frees them.  `stream` is a hipStream_t passed as void*
+ *     (NULL = the default stream); work is enqueued on it.
+ *   - CSR input: rowptr int64[n+1] with rowptr[0] = 0 and non-decreasing,
+ *     col int32[nnz] with 0 <= col < n (any order within a row), val[nnz] in
+ *     the storage precision: double (LZ_FP64), float (LZ_FP32) or bfloat16
+ *     bits as uint16 (LZ_BF16).  The matrix must be symmetric (caller's
+ *     contract; not checked).
+ *   - Limits: n >= 1, 1 <= K <= m <= min(n, LZ_MAX_STEPS), n < 2^31.
+ */
+#ifndef LANCZOS_TOPK_H
+#define LANCZOS_TOPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LZ_MAX_STEPS 64
+
+/* Storage precision of the matrix values and the Lanczos basis (Sec. II-A).
+ * LZ_FP64: values, basis and SpMV accumulation in binary64.
+ * LZ_FP32: values and basis stored binary32, SpMV accumulates in binary32.
+ * LZ_BF16: values and basis stored bfloat16, SpMV accumulates in binary32.
+ * In every mode alpha/beta, the reorthogonalisation coefficients, the Jacobi
+ * solve, the Ritz product and the residual report are binary64. */
+typedef enum { LZ_FP64 = 0, LZ_FP32 = 1, LZ_BF16 = 2 } lz_precision;
+
+typedef enum {
+    LZ_OK = 0,
+    LZ_ERR_INVALID_ARG = -1,        /* null pointer, bad size or precision */
+    LZ_ERR_OUT_OF_MEMORY = -2,      /* library-side allocation failed */
+    LZ_ERR_HIP = -3,                /* a HIP runtime call failed */
+    LZ_ERR_WORKSPACE_TOO_SMALL = -4,
+    LZ_ERR_TOO_LARGE = -5,          /* serving: request exceeds the HBM budget */
+    LZ_ERR_NOT_CONVERGED = -6,      /* Jacobi hit its sweep limit */
+    LZ_ERR_NONFINITE = -7,          /* NaN or Inf appeared in beta */
+    LZ_ERR_BREAKDOWN = -8,          /* a restart vector had no component
+                                       outside the basis */
+    LZ_PENDING = 1                  /* serving: request not finished yet */
+} lz_status;
+
+/* Reorthogonalisation modes (Algorithm 1, orthogonalisation loop). */
+#define LZ_REORTH_NONE 0       /* three-term recurrence only */
+#define LZ_REORTH_ONCE 1       /* one classical Gram-Schmidt pass */
+#define LZ_REORTH_TWICE 2      /* two passes ("twice is enough"); default */
+#define LZ_REORTH_SELECTIVE 3  /* second pass only when its correction
+                                  exceeds the storage rounding of w */
+
+typedef struct lz_options {
+    uint64_t seed;           /* start vector: u_r = U01(SplitMix64(seed, r)),
+                                v_1 = u/||u||; default 0 */
+    int32_t reorth;          /* LZ_REORTH_*; default LZ_REORTH_TWICE */
+    int32_t report;          /* 1 (default): residuals and orthogonality */
+    void* workspace;         /* device memory of workspace_bytes, or NULL:
+                                the library allocates for the call */
+    size_t workspace_bytes;
+} lz_options;
+
+/* Results of one solve, filled on the host when the call returns. */
+typedef struct lz_report {
+    int32_t status;          /* lz_status of the solve */
+    int32_t m_eff;           /* Lanczos steps taken (= m on success) */
+    int32_t restarts;        /* breakdowns met (beta <= tau) */
+    int32_t jacobi_sweeps;
+    double beta_last;        /* beta_{m+1}: norm of the final residual vector */
+    double resid[LZ_MAX_STEPS];      /* ||A y_k - theta_k y_k|| / |theta_k|
+                                        (= the absolute value if theta_k = 0) */
+    double abs_resid[LZ_MAX_STEPS];  /* ||A y_k - theta_k y_k|| (Sec. IV-D) */
+    double ortho_loss;       /* max |V^T V - I| over the m basis vectors */
+    double ritz_ortho_loss;  /* max |Y^T Y - I| over the K Ritz vectors */
+    double mean_angle_deg;   /* mean angle between Ritz vector pairs
+                                (Sec. IV-D; 90 is ideal) */
+    double alpha[LZ_MAX_STEPS];      /* diagonal of T */
+    double beta[LZ_MAX_STEPS + 1];   /* beta[0] = 0, beta[i] couples v_i and
+                                        v_{i+1} (1-based), beta[m] = beta_last */
+    double theta[LZ_MAX_STEPS];      /* all m Ritz values (Jacobi order) */
+} lz_report;
+
+/* Fills *opt with the defaults above. */
+void lz_options_init(lz_options* opt);
+
+/* Human-readable name of a status code (static string). */
+const char* lz_status_string(int status);
+
+/*
+ * Top-K eigenpairs of the symmetric CSR matrix (Sec. II, Algorithm 1 then
+ * Jacobi and the Ritz product), the K eigenvalues of largest modulus.
+ *   out_vals: device double[K], ordered by |lambda| descending, ties by
+ *             lambda descending.
+ *   out_vecs: device double[n*K], column-major (vector k at out_vecs+k*n),
+ *             unit 2-norm, signed so its entry of largest modulus is positive.
+ * Default options; the library allocates its workspace for the call.
+ * Blocking: returns after the results are in out_vals/out_vecs.
+ */
+int lanczos_topk(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val,
+                 int64_t n, int32_t K, int32_t m, int32_t precision, void* stream,
+                 double* out_vals, double* out_vecs);
+
+/* Device bytes of workspace a solve of this shape needs. */
+size_t lanczos_topk_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m,
+                                   int32_t precision);
+
+/*
+ * lanczos_topk with options and a report.  nnz must equal rowptr[n].
+ * opt may be NULL (defaults); report may be NULL.  With a caller workspace
+ * the call allocates nothing.  Blocking like lanczos_topk.
+ */
+int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val,
+                    int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision,
+                    void* stream, double* out_vals, double* out_vecs,
+                    const lz_options* opt, lz_report* report);
+
+/*
+ * y = A x in the given precision (Algorithm 1, the SpMV line), with the
+ * same row partitioning and kernels the solver uses.  x and y are device
+ * arrays of n elements of the storage type (y is double for LZ_FP64, float
+ * otherwise).  The library allocates its scratch for the call.  Blocking.
+ */
+int lz_spmv(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val,
+            int64_t n, int64_t nnz, int32_t precision, const void* x, void* y, void* stream);
+
+/*
+ * Eigen-decomposition of one symmetric tridiagonal matrix by the parallel
+ * Jacobi kernel the solver uses (Sec. II, second phase).  Host arrays:
+ * alpha[m] diagonal, offdiag[m-1]; out theta[m] (unsorted, Jacobi order),
+ * S[m*m] row-major, column k = eigenvector of theta[k].  m <= LZ_MAX_STEPS.
+ * Returns LZ_ERR_NOT_CONVERGED if the sweep limit was hit.  Blocking.
+ */
+int lz_tridiag_eig(const double* alpha, const double* offdiag, int32_t m,
+                   double* theta, double* S, int32_t* sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LANCZOS_TOPK_H */

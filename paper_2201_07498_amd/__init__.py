@@ -1,0 +1,182 @@
+"""Python binding of liblanczos_topk.so, the gfx950 Top-K sparse symmetric
+eigensolver (Lanczos with full reorthogonalisation + Jacobi + Ritz vectors).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device arrays are torch tensors on a ROCm device; streams are torch streams.
+There is no CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblanczos_topk.so")
+
+LZ_FP64, LZ_FP32, LZ_BF16 = 0, 1, 2
+PRECISION = {"fp64": LZ_FP64, "fp32": LZ_FP32, "bf16": LZ_BF16}
+REORTH = {"none": 0, "once": 1, "twice": 2, "selective": 3}
+MAX_STEPS = 64
+STATUS = {0: "LZ_OK", -1: "LZ_ERR_INVALID_ARG", -2: "LZ_ERR_OUT_OF_MEMORY", -3: "LZ_ERR_HIP",
+          -4: "LZ_ERR_WORKSPACE_TOO_SMALL", -5: "LZ_ERR_TOO_LARGE", -6: "LZ_ERR_NOT_CONVERGED",
+          -7: "LZ_ERR_NONFINITE", -8: "LZ_ERR_BREAKDOWN", 1: "LZ_PENDING"}
+
+
+class LanczosError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("reorth", ctypes.c_int32), ("report", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("m_eff", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("jacobi_sweeps", ctypes.c_int32), ("beta_last", ctypes.c_double),
+                ("resid", ctypes.c_double * MAX_STEPS), ("abs_resid", ctypes.c_double * MAX_STEPS),
+                ("ortho_loss", ctypes.c_double), ("ritz_ortho_loss", ctypes.c_double),
+                ("mean_angle_deg", ctypes.c_double), ("alpha", ctypes.c_double * MAX_STEPS),
+                ("beta", ctypes.c_double * (MAX_STEPS + 1)), ("theta", ctypes.c_double * MAX_STEPS)]
+
+    def to_dict(self, K: int, m: int) -> dict:
+        return dict(status=self.status, m_eff=self.m_eff, restarts=self.restarts,
+                    jacobi_sweeps=self.jacobi_sweeps, beta_last=self.beta_last,
+                    resid=np.array(self.resid[:K]), abs_resid=np.array(self.abs_resid[:K]),
+                    ortho_loss=self.ortho_loss, ritz_ortho_loss=self.ritz_ortho_loss,
+                    mean_angle_deg=self.mean_angle_deg, alpha=np.array(self.alpha[:m]),
+                    beta=np.array(self.beta[:m + 1]), theta=np.array(self.theta[:m]))
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+        L.lz_options_init.restype = None
+        L.lz_options_init.argtypes = [ctypes.POINTER(Options)]
+        L.lz_status_string.restype = ctypes.c_char_p
+        L.lz_status_string.argtypes = [ctypes.c_int]
+        L.lanczos_topk.restype = ctypes.c_int
+        L.lanczos_topk.argtypes = [P, P, P, i64, i32, i32, i32, P, P, P]
+        L.lanczos_topk_workspace_size.restype = ctypes.c_size_t
+        L.lanczos_topk_workspace_size.argtypes = [i64, i64, i32, i32, i32]
+        L.lanczos_topk_ex.restype = ctypes.c_int
+        L.lanczos_topk_ex.argtypes = [P, P, P, i64, i64, i32, i32, i32, P, P, P,
+                                      ctypes.POINTER(Options), ctypes.POINTER(Report)]
+        L.lz_spmv.restype = ctypes.c_int
+        L.lz_spmv.argtypes = [P, P, P, i64, i64, i32, P, P, P]
+        L.lz_tridiag_eig.restype = ctypes.c_int
+        L.lz_tridiag_eig.argtypes = [P, P, i32, P, P, ctypes.POINTER(ctypes.c_int32)]
+        _lib = L
+    return _lib
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, str):
+        return PRECISION[precision]
+    return int(precision)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_csr(rowptr, col, val, precision: int):
+    import torch
+    for t, dt, name in ((rowptr, torch.int64, "rowptr"), (col, torch.int32, "col")):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous {dt} device tensor")
+    want = {LZ_FP64: torch.float64, LZ_FP32: torch.float32, LZ_BF16: torch.bfloat16}[precision]
+    if not (val.is_cuda and val.dtype == want and val.is_contiguous()):
+        raise TypeError(f"val must be a contiguous {want} device tensor")
+
+
+def workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
+    return int(lib().lanczos_topk_workspace_size(n, nnz, K, m, _prec(precision)))
+
+
+def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
+         report: bool = True, stream=None, workspace=None, nnz: int | None = None):
+    """Top-K eigenpairs.  Returns (vals[K], vecs[n, K] view of the column-major
+    output, report dict)."""
+    import torch
+    p = _prec(precision)
+    _check_csr(rowptr, col, val, p)
+    n = rowptr.numel() - 1
+    if nnz is None:
+        nnz = col.numel()
+    dev = rowptr.device
+    vals = torch.empty(K, dtype=torch.float64, device=dev)
+    vecs = torch.empty(K, n, dtype=torch.float64, device=dev)
+    opt = Options()
+    lib().lz_options_init(ctypes.byref(opt))
+    opt.seed = seed & (2 ** 64 - 1)
+    opt.reorth = REORTH[reorth] if isinstance(reorth, str) else int(reorth)
+    opt.report = 1 if report else 0
+    if workspace is not None:
+        opt.workspace = ctypes.c_void_p(workspace.data_ptr())
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    rep = Report()
+    rc = lib().lanczos_topk_ex(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, nnz, K, m, p,
+                               _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(),
+                               ctypes.byref(opt), ctypes.byref(rep))
+    if rc != 0:
+        raise LanczosError(rc, "lanczos_topk_ex")
+    return vals, vecs.T, rep.to_dict(K, m)
+
+
+def topk_plain(rowptr, col, val, K: int, m: int, precision="fp64", stream=None):
+    """The minimal entry point lanczos_topk (default options, no report)."""
+    import torch
+    p = _prec(precision)
+    _check_csr(rowptr, col, val, p)
+    n = rowptr.numel() - 1
+    vals = torch.empty(K, dtype=torch.float64, device=rowptr.device)
+    vecs = torch.empty(K, n, dtype=torch.float64, device=rowptr.device)
+    rc = lib().lanczos_topk(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, K, m, p,
+                            _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr())
+    if rc != 0:
+        raise LanczosError(rc, "lanczos_topk")
+    return vals, vecs.T
+
+
+def spmv(rowptr, col, val, x, precision="fp64", stream=None):
+    """y = A x with the solver's SpMV kernels (y is float64 for fp64, else float32)."""
+    import torch
+    p = _prec(precision)
+    _check_csr(rowptr, col, val, p)
+    n = rowptr.numel() - 1
+    y = torch.empty(n, dtype=torch.float64 if p == LZ_FP64 else torch.float32, device=rowptr.device)
+    rc = lib().lz_spmv(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, col.numel(), p,
+                       x.data_ptr(), y.data_ptr(), _stream_ptr(stream))
+    if rc != 0:
+        raise LanczosError(rc, "lz_spmv")
+    return y
+
+
+def tridiag_eig(alpha, offdiag):
+    """Jacobi eigensolve of one symmetric tridiagonal matrix on the GPU."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    m = a.size
+    o = np.ascontiguousarray(offdiag if m > 1 else np.zeros(1), dtype=np.float64)
+    theta = np.zeros(m)
+    S = np.zeros((m, m))
+    sw = ctypes.c_int32(0)
+    rc = lib().lz_tridiag_eig(a.ctypes.data, o.ctypes.data, m, theta.ctypes.data, S.ctypes.data,
+                              ctypes.byref(sw))
+    if rc != 0:
+        raise LanczosError(rc, "lz_tridiag_eig")
+    return theta, S, sw.value

@@ -1,0 +1,277 @@
+// C ABI of the Top-K Lanczos solver: argument checks, workspace planning and
+// the launch sequence of one solve.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lanczos_topk.h"
+#include "lz_internal.h"
+
+namespace lz {
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int pow2_ge(int k) {
+    int v = 1;
+    while (v < k) v <<= 1;
+    return v;
+}
+
+Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
+    Plan p;
+    p.n = n;
+    p.nnz = nnz;
+    p.K = K;
+    p.m = m;
+    p.prec = prec;
+    p.ld = ceil_div(n, LDPAD) * LDPAD;
+    p.KB = (int32_t)std::max<int64_t>(8, ceil_div(K, 8) * 8);
+    p.g_orth = (int32_t)std::min<int64_t>(OGRID, p.ld / BLOCK);
+    p.items_cap = ceil_div(n, RMAX) + 3 * ceil_div(nnz, NB) + ceil_div(nnz, CH) + 2;
+    p.long_cap = nnz / NB + 1;
+    const int64_t est_items = ceil_div(nnz, NB) + ceil_div(n, RMAX);
+    p.g_spmv = (int32_t)std::max<int64_t>(1, std::min<int64_t>(SGRID, est_items));
+    const int kb2 = pow2_ge(K);
+    const size_t vb = storage_bytes(prec), wb = work_bytes(prec);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    p.off_state = take(sizeof(State));
+    p.off_V = take((size_t)p.ld * (size_t)(m + 1) * vb);
+    p.off_w = take((size_t)p.ld * wb);
+    p.off_part = take((size_t)p.g_orth * 256 * 8);
+    p.off_part2 = take((size_t)std::max(p.g_spmv, p.g_orth) * 64 * 8);
+    p.off_items = take((size_t)p.items_cap * 8);
+    p.off_lrow = take((size_t)p.long_cap * 4);
+    p.off_lfirst = take((size_t)p.long_cap * 4);
+    p.off_lnch = take((size_t)p.long_cap * 4);
+    p.off_ltk = take((size_t)p.long_cap * 4);
+    p.off_lpart = take((size_t)p.items_cap * kb2 * 8);
+    p.off_lval = take((size_t)p.long_cap * kb2 * 8);
+    p.off_scan = take((size_t)n * 8);
+    p.off_bsum = take((size_t)(ceil_div(n, 2048) + 1) * 8);
+    p.off_Y = take((size_t)n * (size_t)K * 8);
+    p.off_gram = take(8);
+    p.bytes = o;
+    return p;
+}
+
+Bufs resolve(const Plan& p, void* base) {
+    char* c = (char*)base;
+    Bufs b;
+    b.st = (State*)(c + p.off_state);
+    b.V = c + p.off_V;
+    b.w = c + p.off_w;
+    b.part = (double*)(c + p.off_part);
+    b.part2 = (double*)(c + p.off_part2);
+    b.items = (int2*)(c + p.off_items);
+    b.lrow = (int32_t*)(c + p.off_lrow);
+    b.lfirst = (int32_t*)(c + p.off_lfirst);
+    b.lnch = (int32_t*)(c + p.off_lnch);
+    b.ltk = (uint32_t*)(c + p.off_ltk);
+    b.lpart = (double*)(c + p.off_lpart);
+    b.lval = (double*)(c + p.off_lval);
+    b.scan = (uint64_t*)(c + p.off_scan);
+    b.bsum = (uint64_t*)(c + p.off_bsum);
+    b.Y = (double*)(c + p.off_Y);
+    b.gram = (double*)(c + p.off_gram);
+    return b;
+}
+
+}  // namespace lz
+
+using namespace lz;
+
+#define LZ_HIP(call)                              \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) { rc = LZ_ERR_HIP; goto done; } \
+    } while (0)
+
+static int check_common(const void* rowptr, const void* col, const void* val, int64_t n, int32_t K, int32_t m,
+                        int32_t precision) {
+    if (!rowptr || !col || !val) return LZ_ERR_INVALID_ARG;
+    if (n < 1 || n >= (int64_t(1) << 31)) return LZ_ERR_INVALID_ARG;
+    if (precision < LZ_FP64 || precision > LZ_BF16) return LZ_ERR_INVALID_ARG;
+    if (K < 1 || m < K || m > LZ_MAX_STEPS || (int64_t)m > n) return LZ_ERR_INVALID_ARG;
+    return LZ_OK;
+}
+
+extern "C" {
+
+void lz_options_init(lz_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->seed = 0;
+    opt->reorth = LZ_REORTH_TWICE;
+    opt->report = 1;
+}
+
+const char* lz_status_string(int status) {
+    switch (status) {
+        case LZ_OK: return "ok";
+        case LZ_ERR_INVALID_ARG: return "invalid argument";
+        case LZ_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case LZ_ERR_HIP: return "HIP runtime error";
+        case LZ_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case LZ_ERR_TOO_LARGE: return "request larger than the memory budget";
+        case LZ_ERR_NOT_CONVERGED: return "Jacobi did not converge";
+        case LZ_ERR_NONFINITE: return "non-finite value in the Lanczos recurrence";
+        case LZ_ERR_BREAKDOWN: return "restart vector lies in the Krylov basis";
+        case LZ_PENDING: return "pending";
+        default: return "unknown status";
+    }
+}
+
+size_t lanczos_topk_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision) {
+    if (n < 1 || nnz < 0 || K < 1 || m < K || m > LZ_MAX_STEPS || precision < 0 || precision > 2) return 0;
+    return make_plan(n, nnz, K, m, precision).bytes;
+}
+
+int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n, int64_t nnz,
+                    int32_t K, int32_t m, int32_t precision, void* stream, double* out_vals, double* out_vecs,
+                    const lz_options* opt, lz_report* report) {
+    int rc = check_common(csr_rowptr, csr_col, csr_val, n, K, m, precision);
+    if (rc != LZ_OK) return rc;
+    if (!out_vals || !out_vecs || nnz < 0 || nnz >= (int64_t(1) << 40)) return LZ_ERR_INVALID_ARG;
+    lz_options o;
+    lz_options_init(&o);
+    if (opt) o = *opt;
+    if (o.reorth < LZ_REORTH_NONE || o.reorth > LZ_REORTH_SELECTIVE) return LZ_ERR_INVALID_ARG;
+    const Plan p = make_plan(n, nnz, K, m, precision);
+    if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
+
+    hipStream_t s = (hipStream_t)stream;
+    void* ws = o.workspace;
+    bool owned = false;
+    State* hst = nullptr;
+    {
+        if (!ws) {
+            if (hipMalloc(&ws, p.bytes) != hipSuccess) return LZ_ERR_OUT_OF_MEMORY;
+            owned = true;
+        }
+        const Bufs b = resolve(p, ws);
+        const Csr a{csr_rowptr, csr_col, csr_val, n, nnz};
+        hst = new State;
+        LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, s));
+        LZ_HIP(launch_init(p, b, s));
+        for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, s));
+        // Breakdowns consume iterations without advancing j: run more until
+        // m steps are done (bounded; each round advances j).
+        for (int round = 0; round < 2 * LZ_MAX_STEPS + 2; ++round) {
+            LZ_HIP(hipMemcpyAsync(hst, b.st, sizeof(State), hipMemcpyDeviceToHost, s));
+            LZ_HIP(hipStreamSynchronize(s));
+            if (hst->status != 0 || hst->j >= m) break;
+            const int extra = m - hst->j;
+            for (int t = 0; t < extra; ++t) LZ_HIP(launch_iteration(p, b, a, m, s));
+        }
+        if (hst->status == 0 && hst->j < m) {
+            rc = LZ_ERR_BREAKDOWN;
+            goto done;
+        }
+        if (hst->status == 0) LZ_HIP(launch_finish(p, b, a, out_vals, out_vecs, o.report, s));
+        LZ_HIP(hipMemcpyAsync(hst, b.st, sizeof(State), hipMemcpyDeviceToHost, s));
+        LZ_HIP(hipStreamSynchronize(s));
+        rc = hst->status;
+        if (report) {
+            std::memset(report, 0, sizeof(*report));
+            report->status = hst->status;
+            report->m_eff = std::min(hst->j, m);
+            report->restarts = hst->restarts;
+            report->jacobi_sweeps = hst->sweeps;
+            report->beta_last = hst->beta[m];
+            for (int k = 0; k < K; ++k) {
+                report->resid[k] = hst->resid[k];
+                report->abs_resid[k] = hst->abs_resid[k];
+            }
+            for (int i = 0; i < m; ++i) {
+                report->alpha[i] = hst->alpha[i];
+                report->theta[i] = hst->theta[i];
+            }
+            for (int i = 0; i <= m; ++i) report->beta[i] = hst->beta[i];
+            report->ortho_loss = hst->ortho_loss;
+            report->ritz_ortho_loss = hst->ritz_ortho_loss;
+            report->mean_angle_deg = hst->mean_angle_deg;
+        }
+    }
+done:
+    if (owned) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ws);
+    }
+    delete hst;
+    return rc;
+}
+
+int lanczos_topk(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n, int32_t K,
+                 int32_t m, int32_t precision, void* stream, double* out_vals, double* out_vecs) {
+    int rc = check_common(csr_rowptr, csr_col, csr_val, n, K, m, precision);
+    if (rc != LZ_OK) return rc;
+    int64_t nnz = -1;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&nnz, csr_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return LZ_ERR_HIP;
+    return lanczos_topk_ex(csr_rowptr, csr_col, csr_val, n, nnz, K, m, precision, stream, out_vals, out_vecs,
+                           nullptr, nullptr);
+}
+
+int lz_spmv(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n, int64_t nnz,
+            int32_t precision, const void* x, void* y, void* stream) {
+    if (!csr_rowptr || !csr_col || !csr_val || !x || !y) return LZ_ERR_INVALID_ARG;
+    if (n < 1 || n >= (int64_t(1) << 31) || nnz < 0 || precision < 0 || precision > 2) return LZ_ERR_INVALID_ARG;
+    const Plan p = make_plan(n, nnz, 1, 1, precision);
+    hipStream_t s = (hipStream_t)stream;
+    void* ws = nullptr;
+    int rc = LZ_OK;
+    State hst;
+    if (hipMalloc(&ws, p.bytes) != hipSuccess) return LZ_ERR_OUT_OF_MEMORY;
+    {
+        const Bufs b = resolve(p, ws);
+        const Csr a{csr_rowptr, csr_col, csr_val, n, nnz};
+        LZ_HIP(launch_setup(p, b, a, 0, LZ_REORTH_TWICE, s));
+        LZ_HIP(launch_spmv_plain(p, b, a, x, y, s));
+        LZ_HIP(hipMemcpyAsync(&hst, b.st, sizeof(State), hipMemcpyDeviceToHost, s));
+        LZ_HIP(hipStreamSynchronize(s));
+        rc = hst.status;
+    }
+done:
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    return rc;
+}
+
+int lz_tridiag_eig(const double* alpha, const double* offdiag, int32_t m, double* theta, double* S, int32_t* sweeps) {
+    if (!alpha || !theta || !S || m < 1 || m > LZ_MAX_STEPS || (m > 1 && !offdiag)) return LZ_ERR_INVALID_ARG;
+    int rc = LZ_OK;
+    char* d = nullptr;
+    State* hst = new State;
+    const size_t so = align_up(sizeof(State), 256);
+    if (hipMalloc((void**)&d, so + 2 * 64 * 8) != hipSuccess) {
+        delete hst;
+        return LZ_ERR_OUT_OF_MEMORY;
+    }
+    {
+        State* st = (State*)d;
+        double* da = (double*)(d + so);
+        double* dof = da + 64;
+        LZ_HIP(hipMemcpy(da, alpha, m * 8, hipMemcpyHostToDevice));
+        if (m > 1) LZ_HIP(hipMemcpy(dof, offdiag, (m - 1) * 8, hipMemcpyHostToDevice));
+        LZ_HIP(launch_jacobi_only(da, dof, m, st, nullptr));
+        LZ_HIP(hipMemcpy(hst, st, sizeof(State), hipMemcpyDeviceToHost));
+        for (int i = 0; i < m; ++i) theta[i] = hst->theta[i];
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < m; ++c) S[r * m + c] = hst->S[r * MMAX + c];
+        if (sweeps) *sweeps = hst->sweeps;
+        rc = hst->status;
+    }
+done:
+    (void)hipFree(d);
+    delete hst;
+    return rc;
+}
+
+}  // extern "C"

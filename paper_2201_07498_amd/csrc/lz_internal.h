@@ -1,0 +1,121 @@
+// Internal declarations of the gfx950 Lanczos/Jacobi Top-K solver: the
+// device-resident solve state, the workspace plan, precision traits and the
+// kernel launchers.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lz {
+
+constexpr int MMAX = 64;       // largest m (Lanczos steps); Jacobi tile in LDS
+constexpr int NCMAX = 72;      // column bound of the orthogonalisation kernels (m+1 rounded to 8)
+constexpr int BLOCK = 256;     // threads per workgroup (4 wave64)
+constexpr int NB = 1024;       // target non-zeros per row-block work item
+constexpr int CH = 4096;       // non-zeros per chunk of a long row
+constexpr int RMAX = 256;      // rows per row-block work item at most
+constexpr int LDPAD = 2048;    // basis leading dimension is a multiple of this
+constexpr int OGRID = 1024;    // orthogonalisation grid cap (workgroups)
+constexpr int SGRID = 2048;    // SpMV grid cap (workgroups)
+
+enum Mode { MODE_NORMAL = 0, MODE_RESTART = 1 };
+
+// Tickets of the "last workgroup reduces" pattern, one per kernel kind.
+enum Ticket { TK_INIT = 0, TK_SPMV, TK_DOT, TK_UPD, TK_STORE, TK_RITZ, TK_RESID, TK_GRAM, TK_COUNT };
+
+// Solve state kept in device memory; every kernel reads the step index and
+// coefficients from here, so the host never has to read them back between
+// kernels.  Basis column k is stored unnormalised; its unit vector is
+// scale[k] * V[:,k].
+struct State {
+    int32_t j;            // current Lanczos index (0-based): columns 0..j hold v_1..v_{j+1}
+    int32_t mode;         // MODE_NORMAL or MODE_RESTART (next SpMV step draws a restart vector)
+    int32_t restarts;
+    int32_t status;       // lz_status
+    int32_t m, K, reorth, second;   // `second`: run the second update of this step
+    int32_t n_items, n_long, sweeps, pad0;
+    uint32_t ticket[TK_COUNT];
+    uint64_t seed;
+    double u_s;           // unit roundoff of the stored basis
+    double tnorm;         // max_j (|alpha_j| + beta_j), scales the breakdown threshold
+    double wnorm2;        // ||w'||^2 after the first update (selective second pass)
+    double alpha[MMAX + 8];
+    double beta[MMAX + 8];     // beta[k] couples columns k-1 and k; beta[0] = 0
+    double scale[MMAX + 8];
+    double c[NCMAX];           // first-pass projection coefficients (already scaled)
+    double c2[NCMAX];          // second-pass coefficients
+    double theta[MMAX];        // Ritz values (Jacobi order)
+    int32_t sel[MMAX];         // Top-K indices into theta
+    double ysc[MMAX];          // Ritz column scale: sign / norm
+    double abs_resid[MMAX], resid[MMAX];
+    double ortho_loss, ritz_ortho_loss, mean_angle_deg, pad1;
+    double S[MMAX * MMAX];     // Jacobi eigenvectors, row-major m x m (stride MMAX)
+};
+
+// Workspace layout of one solve.  All offsets are in bytes from the base.
+struct Plan {
+    int64_t n = 0, nnz = 0, ld = 0;
+    int32_t K = 0, m = 0, prec = 0, KB = 0;
+    int32_t g_spmv = 0, g_orth = 0;
+    int64_t items_cap = 0, long_cap = 0;
+    size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_items = 0,
+           off_lrow = 0, off_lfirst = 0, off_lnch = 0, off_ltk = 0, off_lpart = 0, off_lval = 0,
+           off_scan = 0, off_bsum = 0, off_Y = 0, off_gram = 0;
+    size_t bytes = 0;
+};
+
+inline size_t storage_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+inline size_t work_bytes(int prec) { return prec == 0 ? 8 : 4; }
+inline double unit_roundoff(int prec) {
+    return prec == 0 ? 1.1102230246251565e-16 : (prec == 1 ? 5.9604644775390625e-08 : 3.90625e-03);
+}
+
+Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec);
+
+// Device pointers of a solve, resolved from a plan and a workspace base.
+struct Bufs {
+    State* st;
+    void* V;
+    void* w;
+    double* part;      // per-workgroup partial sums (g_orth * NCMAX or g_spmv)
+    double* part2;     // second partial buffer (SpMV long rows, residual)
+    int2* items;
+    int32_t* lrow;
+    int32_t* lfirst;
+    int32_t* lnch;
+    uint32_t* ltk;
+    double* lpart;     // long-row chunk partials (items_cap * KB)
+    double* lval;      // per-long-row epilogue values (long_cap * KB)
+    uint64_t* scan;
+    uint64_t* bsum;
+    double* Y;         // Ritz vectors, row-major n x K
+    double* gram;      // Gram partials
+};
+Bufs resolve(const Plan& p, void* base);
+
+// Matrix pointers.
+struct Csr {
+    const int64_t* rowptr;
+    const int32_t* col;
+    const void* val;
+    int64_t n, nnz;
+};
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth,
+                        hipStream_t s);
+hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s);
+// One Lanczos iteration (SpMV or restart draw, two CGS passes, store).
+// `ncols_bound` >= j+1 for every j the iteration can see.
+hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols_bound,
+                            hipStream_t s);
+hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
+                         double* out_vecs, int report, hipStream_t s);
+hipError_t launch_spmv_plain(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y,
+                             hipStream_t s);
+hipError_t launch_jacobi_only(const double* alpha, const double* offdiag, int m, State* st,
+                              hipStream_t s);
+
+}  // namespace lz

@@ -1,0 +1,69 @@
+"""The C ABI library loads and exports every entry point its header declares;
+argument errors are reported before any GPU work (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2201_07498_amd as lz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lanczos_topk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("lanczos_topk", "lanczos_topk_ex", "lanczos_topk_workspace_size", "lz_options_init",
+                 "lz_status_string", "lz_spmv", "lz_tridiag_eig"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lz.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_defaults():
+    L = lz.lib()
+    assert L.lz_status_string(0) == b"ok"
+    assert L.lz_status_string(-1) == b"invalid argument"
+    opt = lz.Options()
+    L.lz_options_init(ctypes.byref(opt))
+    assert opt.reorth == 2 and opt.report == 1 and opt.seed == 0 and not opt.workspace
+
+
+@pytest.mark.parametrize("n,K,m,prec", [(0, 1, 1, 0), (10, 0, 1, 0), (10, 3, 2, 0), (10, 1, 65, 0),
+                                         (10, 4, 11, 0), (10, 1, 2, 3), (10, 1, 2, -1)])
+def test_invalid_arguments_rejected_without_gpu(n, K, m, prec):
+    L = lz.lib()
+    dummy = ctypes.c_void_p(16)
+    rc = L.lanczos_topk(dummy, dummy, dummy, n, K, m, prec, None, dummy, dummy)
+    assert rc == -1
+    rc = L.lanczos_topk_ex(dummy, dummy, dummy, n, 100, K, m, prec, None, dummy, dummy, None, None)
+    assert rc == -1
+
+
+def test_null_pointers_rejected():
+    L = lz.lib()
+    d = ctypes.c_void_p(16)
+    assert L.lanczos_topk(None, d, d, 10, 1, 2, 0, None, d, d) == -1
+    assert L.lanczos_topk_ex(d, d, d, 10, 5, 1, 2, 0, None, None, d, None, None) == -1
+    assert L.lz_spmv(d, None, d, 10, 5, 0, d, d, None) == -1
+    assert L.lz_tridiag_eig(None, None, 3, None, None, None) == -1
+
+
+def test_workspace_size_grows_with_shape():
+    a = lz.workspace_size(10000, 100000, 8, 24, "fp64")
+    b = lz.workspace_size(10000, 100000, 8, 24, "fp32")
+    c = lz.workspace_size(20000, 200000, 8, 24, "fp64")
+    assert a > 10000 * 25 * 8 and b < a and c > a
+    assert lz.workspace_size(0, 1, 1, 1, "fp64") == 0

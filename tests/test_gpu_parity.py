@@ -1,0 +1,177 @@
+"""GPU parity: the HIP library, called through its C ABI, against the FP64 CPU
+oracle on the same seeded inputs.
+
+Tolerances:
+  * SpMV: per row |y - y_ref| <= c * len * u_acc * sum_k |a_k x_k| (rounding
+    of a length-len dot product in the accumulation precision).
+  * Eigenvalues: relative error <= 1e-10 (FP64), 1e-6 (FP32 storage),
+    1e-3 (BF16 storage), the bounds the solver is specified to meet.
+  * Jacobi alone: eigenvalues within 1e-13 ||T||.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import device_csr, device_values, eig_rel_err, multiset_rel_err, subspace_cos
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2201_07498_amd as lz  # noqa: E402
+
+U_ACC = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16": 2.0 ** -24}
+EIG_TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16": 1e-3}
+
+
+def spmv_cases():
+    cases = {}
+    cases["er5000"] = synth.er(5000, 9.0, seed=11)
+    cases["rmat14"] = synth.rmat(14, 8, seed=12)
+    # One hub row with 10 000 non-zeros (three chunks) plus a sparse tail.
+    rp, c, v = synth.star(10000)
+    cases["star10000"] = (rp, c, np.random.default_rng(3).uniform(0, 1, c.size))
+    cases["path3"] = synth.path(3)
+    cases["single"] = synth.diagonal([2.5])
+    # Rows of every length class, with empty rows between them.
+    rng = np.random.default_rng(5)
+    n = 6000
+    edges = set()
+    for hub, deg in ((17, 1500), (2048, 5000), (4095, 900), (5999, 4097)):
+        for t in rng.choice(n, deg, replace=False):
+            if t != hub:
+                edges.add((min(hub, t), max(hub, t)))
+    for i in range(0, n, 7):
+        edges.add((i, (i * 31 + 5) % n) if i != (i * 31 + 5) % n else (i, (i + 1) % n))
+    edges = sorted(e for e in edges if e[0] != e[1])
+    cases["mixed6000"] = synth.from_edges(n, edges, weights=rng.uniform(-1, 1, len(edges)))
+    return cases
+
+
+SPMV = spmv_cases()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("name", sorted(SPMV))
+def test_spmv_matches_oracle(name, precision):
+    rp, c, v = SPMV[name]
+    n = rp.size - 1
+    print(f"spmv {name} n={n} nnz={rp[-1]} {precision}", flush=True)
+    vr = synth.round_values(v, precision)
+    x = synth.round_values(np.random.default_rng(1).uniform(-1, 1, n), precision)
+    drp, dc, dv = device_csr(rp, c, vr, precision)
+    dx = device_values(x, precision)
+    y = lz.spmv(drp, dc, dv, dx, precision).double().cpu().numpy()
+    want = oracle.spmv(rp, c, vr, x)
+    mag = oracle.spmv(rp, c, np.abs(vr), np.abs(x))
+    lens = np.diff(rp)
+    bound = 2.0 * (lens + 2) * U_ACC[precision] * mag + 1e-300
+    assert np.all(np.abs(y - want) <= bound), np.max(np.abs(y - want) / bound)
+
+
+@pytest.mark.parametrize("m,seed", [(1, 0), (2, 1), (7, 2), (24, 3), (48, 4), (64, 5)])
+def test_tridiagonal_jacobi_matches_oracle(m, seed):
+    rng = np.random.default_rng(seed)
+    a, b = rng.uniform(-2, 2, m), rng.uniform(0.05, 1, max(m - 1, 0))
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    theta, S, sweeps = lz.tridiag_eig(a, b)
+    ref, _, _ = oracle.jacobi(T)
+    nrm = max(1.0, np.linalg.norm(T, 2))
+    assert np.max(np.abs(np.sort(theta) - np.sort(ref))) <= 1e-13 * nrm
+    assert np.max(np.abs(S.T @ S - np.eye(m))) <= 1e-13
+    assert np.max(np.abs(T @ S - S * theta)) <= 1e-13 * nrm
+    assert 1 <= sweeps <= 20
+
+
+def run_gpu(rp, c, v, K, m, precision="fp64", seed=0, reorth="twice"):
+    drp, dc, dv = device_csr(rp, c, v, precision)
+    vals, vecs, rep = lz.topk(drp, dc, dv, K, m, precision, seed=seed, reorth=reorth)
+    torch.cuda.synchronize()
+    return vals.cpu().numpy(), vecs.cpu().numpy(), rep
+
+
+def test_fp64_er10000_k8_m24_matches_oracle():
+    # Erdos-Renyi n=10 000, ~10 nnz/row, K=8, m=24, seed 0, FP64 everywhere.
+    rp, c, v = synth.er(10000, 9.0, seed=0)
+    K, m = 8, 24
+    vals, Y, rep = run_gpu(rp, c, v, K, m, "fp64", seed=0)
+    ref = oracle.topk(rp, c, v, K, m, seed=0)
+    err = eig_rel_err(vals, ref["vals"])
+    print(f"fp64 er10000 eig rel err {err:.3e} resid {rep['resid'].max():.3e} ortho {rep['ortho_loss']:.2e}")
+    assert err <= 1e-10
+    np.testing.assert_allclose(rep["alpha"], ref["alpha"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(rep["beta"], ref["beta"], rtol=1e-12, atol=1e-13)
+    cos = np.abs(np.sum(Y * ref["vecs"], axis=0))
+    assert np.all(cos >= 1 - 1e-9), cos
+    np.testing.assert_allclose(rep["abs_resid"], ref["abs_resid"], rtol=1e-7)
+    assert rep["restarts"] == 0 and rep["m_eff"] == m
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 37, 2047, 2049, 4097])
+def test_ragged_sizes(n):
+    rp, c, v = synth.er(n, min(9.0, max(n - 1, 0)), seed=n)
+    m = min(n, 10)
+    K = min(m, 3)
+    vals, Y, rep = run_gpu(rp, c, v, K, m, "fp64", seed=2)
+    ref = oracle.topk(rp, c, v, K, m, seed=2)
+    assert multiset_rel_err(vals, ref["vals"]) <= 1e-10
+    assert rep["m_eff"] == m
+
+
+CLOSED = {
+    "complete12": (synth.complete(12), [11.0] + [-1.0] * 11),
+    "star9": (synth.star(9), [3.0, -3.0] + [0.0] * 8),
+    "cycle20": (synth.cycle(20), [2 * np.cos(2 * np.pi * k / 20) for k in range(20)]),
+    "hypercube4": (synth.hypercube(4), [4.0] + [2.0] * 4 + [0.0] * 6 + [-2.0] * 4 + [-4.0]),
+    "path25": (synth.path(25), [2 * np.cos(np.pi * k / 26) for k in range(1, 26)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CLOSED))
+def test_closed_form_spectra_with_restarts(name):
+    (rp, c, v), lam = CLOSED[name]
+    n = rp.size - 1
+    vals, Y, rep = run_gpu(rp, c, v, n, n, "fp64", seed=3)
+    ref = oracle.topk(rp, c, v, n, n, seed=3)
+    assert np.max(np.abs(np.sort(rep["theta"]) - np.sort(lam))) <= 1e-10 * max(1, np.max(np.abs(lam)))
+    assert rep["restarts"] == ref["restarts"]
+    assert np.max(np.abs(np.abs(vals) - np.abs(ref["vals"]))) <= 1e-10
+
+
+def test_deterministic_bitwise():
+    rp, c, v = synth.rmat(13, 8, seed=4)
+    a = run_gpu(rp, c, v, 6, 20, "fp64", seed=9)
+    b = run_gpu(rp, c, v, 6, 20, "fp64", seed=9)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2]["alpha"], b[2]["alpha"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_mixed_precision_er_accuracy(precision):
+    rp, c, v = synth.er(10000, 9.0, seed=0)
+    v = synth.round_values(v, precision)
+    K, m = 8, 24
+    vals, Y, rep = run_gpu(rp, c, v, K, m, precision, seed=0)
+    ref = oracle.topk(rp, c, v, K, m, seed=0)
+    err = eig_rel_err(vals, ref["vals"])
+    print(f"{precision} er10000 eig rel err {err:.3e} ortho {rep['ortho_loss']:.2e} resid {rep['resid'].max():.2e}")
+    assert err <= EIG_TOL[precision]
+
+
+@pytest.mark.parametrize("reorth", ["none", "once", "selective"])
+def test_reorth_modes_run(reorth):
+    rp, c, v = synth.er(4000, 9.0, seed=7)
+    K, m = 4, 20
+    vals, Y, rep = run_gpu(rp, c, v, K, m, "fp64", seed=7, reorth=reorth)
+    passes = {"none": 0, "once": 1, "selective": 2}[reorth]
+    ref = oracle.topk(rp, c, v, K, m, seed=7, passes=passes)
+    assert eig_rel_err(vals, ref["vals"]) <= 1e-9
+
+
+def test_plain_entry_point_matches_ex():
+    rp, c, v = synth.er(3000, 9.0, seed=0)
+    drp, dc, dv = device_csr(rp, c, v, "fp64")
+    vals, vecs = lz.topk_plain(drp, dc, dv, 4, 12, "fp64")
+    vals2, vecs2, _ = lz.topk(drp, dc, dv, 4, 12, "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(vals, vals2) and torch.equal(vecs, vecs2)
