@@ -74,6 +74,9 @@ typedef struct lz_options {
     void* workspace;         /* device memory of workspace_bytes, or NULL:
                                 the library allocates for the call */
     size_t workspace_bytes;
+    int32_t profile;         /* 1: time the phases with HIP events recorded
+                                on `stream` (fills the t_* report fields) */
+    int32_t reserved;
 } lz_options;
 
 /* Results of one solve, filled on the host when the call returns. */
@@ -94,6 +97,12 @@ typedef struct lz_report {
     double beta[LZ_MAX_STEPS + 1];   /* beta[0] = 0, beta[i] couples v_i and
                                         v_{i+1} (1-based), beta[m] = beta_last */
     double theta[LZ_MAX_STEPS];      /* all m Ritz values (Jacobi order) */
+    /* Phase timings in milliseconds (only with lz_options.profile = 1). */
+    double t_setup_ms;       /* input checks, row partition, start vector */
+    double t_lanczos_ms;     /* all Lanczos iterations */
+    double t_spmv_ms;        /* mean duration of one SpMV launch */
+    double t_orth_ms;        /* mean duration of one step's reorthogonalisation */
+    double t_finish_ms;      /* Jacobi, selection, Ritz vectors, report */
 } lz_report;
 
 /* Fills *opt with the defaults above. */
@@ -148,6 +157,15 @@ int lz_spmv(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_v
  */
 int lz_tridiag_eig(const double* alpha, const double* offdiag, int32_t m,
                    double* theta, double* S, int32_t* sweeps);
+
+/*
+ * Orthogonality loss max_{i,j} |(X^T X - I)_{ij}| of c <= LZ_MAX_STEPS
+ * columns of a column-major device matrix X (leading dimension ldx >= n,
+ * storage type of `precision`), computed by the Gram kernel of the solve
+ * report (Sec. IV-D: orthogonality of the computed vectors).  Blocking.
+ */
+int lz_ortho_loss(const void* X, int64_t ldx, int64_t n, int32_t c, int32_t precision, void* stream,
+                  double* out_loss);
 
 #ifdef __cplusplus
 }

@@ -188,6 +188,8 @@ def mean_angle_deg(Y) -> float:
 def topk(rowptr, col, val, K: int, m: int, seed: int = 0, passes: int = 2,
          unit_roundoff: float = 2.0 ** -53, report: bool = True) -> dict:
     """The whole solve: Lanczos, Jacobi on T, Top-K, Ritz vectors, report."""
+    if not (1 <= K <= m <= rowptr.size - 1):
+        raise ValueError("need 1 <= K <= m <= n")
     alpha, beta, V, restarts = lanczos(rowptr, col, val, m, seed, passes, unit_roundoff)
     T = tridiag(alpha, beta)
     theta, S, sweeps = jacobi(T)

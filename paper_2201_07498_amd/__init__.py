@@ -32,7 +32,8 @@ class LanczosError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("reorth", ctypes.c_int32), ("report", ctypes.c_int32),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -41,7 +42,10 @@ class Report(ctypes.Structure):
                 ("resid", ctypes.c_double * MAX_STEPS), ("abs_resid", ctypes.c_double * MAX_STEPS),
                 ("ortho_loss", ctypes.c_double), ("ritz_ortho_loss", ctypes.c_double),
                 ("mean_angle_deg", ctypes.c_double), ("alpha", ctypes.c_double * MAX_STEPS),
-                ("beta", ctypes.c_double * (MAX_STEPS + 1)), ("theta", ctypes.c_double * MAX_STEPS)]
+                ("beta", ctypes.c_double * (MAX_STEPS + 1)), ("theta", ctypes.c_double * MAX_STEPS),
+                ("t_setup_ms", ctypes.c_double), ("t_lanczos_ms", ctypes.c_double),
+                ("t_spmv_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double),
+                ("t_finish_ms", ctypes.c_double)]
 
     def to_dict(self, K: int, m: int) -> dict:
         return dict(status=self.status, m_eff=self.m_eff, restarts=self.restarts,
@@ -49,7 +53,9 @@ class Report(ctypes.Structure):
                     resid=np.array(self.resid[:K]), abs_resid=np.array(self.abs_resid[:K]),
                     ortho_loss=self.ortho_loss, ritz_ortho_loss=self.ritz_ortho_loss,
                     mean_angle_deg=self.mean_angle_deg, alpha=np.array(self.alpha[:m]),
-                    beta=np.array(self.beta[:m + 1]), theta=np.array(self.theta[:m]))
+                    beta=np.array(self.beta[:m + 1]), theta=np.array(self.theta[:m]),
+                    t_setup_ms=self.t_setup_ms, t_lanczos_ms=self.t_lanczos_ms,
+                    t_spmv_ms=self.t_spmv_ms, t_orth_ms=self.t_orth_ms, t_finish_ms=self.t_finish_ms)
 
 
 _lib = None
@@ -76,6 +82,8 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(Options), ctypes.POINTER(Report)]
         L.lz_spmv.restype = ctypes.c_int
         L.lz_spmv.argtypes = [P, P, P, i64, i64, i32, P, P, P]
+        L.lz_ortho_loss.restype = ctypes.c_int
+        L.lz_ortho_loss.argtypes = [P, i64, i64, i32, i32, P, ctypes.POINTER(ctypes.c_double)]
         L.lz_tridiag_eig.restype = ctypes.c_int
         L.lz_tridiag_eig.argtypes = [P, P, i32, P, P, ctypes.POINTER(ctypes.c_int32)]
         _lib = L
@@ -109,7 +117,8 @@ def workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
 
 
 def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
-         report: bool = True, stream=None, workspace=None, nnz: int | None = None):
+         report: bool = True, stream=None, workspace=None, nnz: int | None = None,
+         profile: bool = False, out=None):
     """Top-K eigenpairs.  Returns (vals[K], vecs[n, K] view of the column-major
     output, report dict)."""
     import torch
@@ -119,13 +128,17 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
     if nnz is None:
         nnz = col.numel()
     dev = rowptr.device
-    vals = torch.empty(K, dtype=torch.float64, device=dev)
-    vecs = torch.empty(K, n, dtype=torch.float64, device=dev)
+    if out is None:
+        vals = torch.empty(K, dtype=torch.float64, device=dev)
+        vecs = torch.empty(K, n, dtype=torch.float64, device=dev)
+    else:
+        vals, vecs = out
     opt = Options()
     lib().lz_options_init(ctypes.byref(opt))
     opt.seed = seed & (2 ** 64 - 1)
     opt.reorth = REORTH[reorth] if isinstance(reorth, str) else int(reorth)
     opt.report = 1 if report else 0
+    opt.profile = 1 if profile else 0
     if workspace is not None:
         opt.workspace = ctypes.c_void_p(workspace.data_ptr())
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -180,3 +193,18 @@ def tridiag_eig(alpha, offdiag):
     if rc != 0:
         raise LanczosError(rc, "lz_tridiag_eig")
     return theta, S, sw.value
+
+
+def ortho_loss(X, precision="fp64", stream=None) -> float:
+    """max |X^T X - I| of the columns of a device matrix X (n x c, column-major
+    storage: pass the transpose view of a contiguous (c, n) tensor)."""
+    import torch
+    p = _prec(precision)
+    n, c = X.shape
+    if X.stride(0) != 1:
+        raise TypeError("X must be column-major (stride 1 along rows)")
+    out = ctypes.c_double(0.0)
+    rc = lib().lz_ortho_loss(X.data_ptr(), X.stride(1), n, c, p, _stream_ptr(stream), ctypes.byref(out))
+    if rc != 0:
+        raise LanczosError(rc, "lz_ortho_loss")
+    return out.value

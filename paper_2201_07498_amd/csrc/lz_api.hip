@@ -42,19 +42,19 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_state = take(sizeof(State));
     p.off_V = take((size_t)p.ld * (size_t)(m + 1) * vb);
     p.off_w = take((size_t)p.ld * wb);
-    p.off_part = take((size_t)p.g_orth * 256 * 8);
+    p.off_part = take((size_t)std::max(p.g_orth, 256) * 256 * 8);
     p.off_part2 = take((size_t)std::max(p.g_spmv, p.g_orth) * 64 * 8);
     p.off_items = take((size_t)p.items_cap * 8);
     p.off_lrow = take((size_t)p.long_cap * 4);
     p.off_lfirst = take((size_t)p.long_cap * 4);
     p.off_lnch = take((size_t)p.long_cap * 4);
-    p.off_ltk = take((size_t)p.long_cap * 4);
-    p.off_lpart = take((size_t)p.items_cap * kb2 * 8);
+    p.off_ltk = take((size_t)p.long_cap * (size_t)K * 4);
+    p.off_lpart = take((size_t)p.items_cap * (size_t)kb2 * 8);
     p.off_lval = take((size_t)p.long_cap * kb2 * 8);
     p.off_scan = take((size_t)n * 8);
     p.off_bsum = take((size_t)(ceil_div(n, 2048) + 1) * 8);
     p.off_Y = take((size_t)n * (size_t)K * 8);
-    p.off_gram = take(8);
+    p.off_gram = take((size_t)(GRAM_PARTS + 1) * 64 * 64 * 8);
     p.bytes = o;
     return p;
 }
@@ -148,6 +148,18 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
     void* ws = o.workspace;
     bool owned = false;
     State* hst = nullptr;
+    hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> iev;       // three per launched iteration when profiling
+    int launched = m;
+    auto iter_events = [&](int t) -> hipEvent_t* {
+        if (!o.profile) return nullptr;
+        while ((int)iev.size() < 3 * (t + 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            iev.push_back(e);
+        }
+        return &iev[3 * t];
+    };
     {
         if (!ws) {
             if (hipMalloc(&ws, p.bytes) != hipSuccess) return LZ_ERR_OUT_OF_MEMORY;
@@ -156,9 +168,14 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         const Bufs b = resolve(p, ws);
         const Csr a{csr_rowptr, csr_col, csr_val, n, nnz};
         hst = new State;
+        if (o.profile) {
+            for (int i = 0; i < 4; ++i) LZ_HIP(hipEventCreate(&pev[i]));
+            LZ_HIP(hipEventRecord(pev[0], s));
+        }
         LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, s));
         LZ_HIP(launch_init(p, b, s));
-        for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, s));
+        if (o.profile) LZ_HIP(hipEventRecord(pev[1], s));
+        for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, s, iter_events(t)));
         // Breakdowns consume iterations without advancing j: run more until
         // m steps are done (bounded; each round advances j).
         for (int round = 0; round < 2 * LZ_MAX_STEPS + 2; ++round) {
@@ -166,13 +183,16 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             LZ_HIP(hipStreamSynchronize(s));
             if (hst->status != 0 || hst->j >= m) break;
             const int extra = m - hst->j;
-            for (int t = 0; t < extra; ++t) LZ_HIP(launch_iteration(p, b, a, m, s));
+            for (int t = 0; t < extra; ++t) LZ_HIP(launch_iteration(p, b, a, m, s, iter_events(launched + t)));
+            launched += extra;
         }
         if (hst->status == 0 && hst->j < m) {
             rc = LZ_ERR_BREAKDOWN;
             goto done;
         }
+        if (o.profile) LZ_HIP(hipEventRecord(pev[2], s));
         if (hst->status == 0) LZ_HIP(launch_finish(p, b, a, out_vals, out_vecs, o.report, s));
+        if (o.profile) LZ_HIP(hipEventRecord(pev[3], s));
         LZ_HIP(hipMemcpyAsync(hst, b.st, sizeof(State), hipMemcpyDeviceToHost, s));
         LZ_HIP(hipStreamSynchronize(s));
         rc = hst->status;
@@ -195,6 +215,21 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             report->ortho_loss = hst->ortho_loss;
             report->ritz_ortho_loss = hst->ritz_ortho_loss;
             report->mean_angle_deg = hst->mean_angle_deg;
+            if (o.profile && launched > 0) {
+                float ms = 0.f;
+                double sp = 0.0, orth = 0.0;
+                for (int t = 0; t < launched; ++t) {
+                    hipEvent_t* e = &iev[3 * t];
+                    if (hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) sp += ms;
+                    if (hipEventElapsedTime(&ms, e[1], e[2]) == hipSuccess) orth += ms;
+                }
+                report->t_spmv_ms = sp / launched;
+                report->t_orth_ms = orth / launched;
+                if (hipEventElapsedTime(&ms, pev[0], pev[1]) == hipSuccess) report->t_setup_ms = ms;
+                if (hipEventElapsedTime(&ms, iev[0], iev[3 * launched - 1]) == hipSuccess)
+                    report->t_lanczos_ms = ms;
+                if (hipEventElapsedTime(&ms, pev[2], pev[3]) == hipSuccess) report->t_finish_ms = ms;
+            }
         }
     }
 done:
@@ -202,6 +237,9 @@ done:
         (void)hipStreamSynchronize(s);
         (void)hipFree(ws);
     }
+    for (hipEvent_t e : iev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : pev)
+        if (e) (void)hipEventDestroy(e);
     delete hst;
     return rc;
 }
@@ -269,6 +307,38 @@ int lz_tridiag_eig(const double* alpha, const double* offdiag, int32_t m, double
         rc = hst->status;
     }
 done:
+    (void)hipFree(d);
+    delete hst;
+    return rc;
+}
+
+int lz_ortho_loss(const void* X, int64_t ldx, int64_t n, int32_t c, int32_t precision, void* stream,
+                  double* out_loss) {
+    if (!X || !out_loss || n < 1 || ldx < n || c < 1 || c > LZ_MAX_STEPS || precision < 0 || precision > 2)
+        return LZ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t so = align_up(sizeof(State), 256);
+    char* d = nullptr;
+    int rc = LZ_OK;
+    State* hst = new State;
+    std::memset(hst, 0, sizeof(State));
+    hst->j = c;
+    hst->m = c;
+    for (int k = 0; k < c; ++k) hst->scale[k] = 1.0;
+    if (hipMalloc((void**)&d, so + (size_t)(GRAM_PARTS + 1) * 64 * 64 * 8) != hipSuccess) {
+        delete hst;
+        return LZ_ERR_OUT_OF_MEMORY;
+    }
+    {
+        State* st = (State*)d;
+        LZ_HIP(hipMemcpyAsync(st, hst, sizeof(State), hipMemcpyHostToDevice, s));
+        LZ_HIP(launch_gram_only(precision, X, ldx, n, st, (double*)(d + so), s));
+        LZ_HIP(hipMemcpyAsync(hst, st, sizeof(State), hipMemcpyDeviceToHost, s));
+        LZ_HIP(hipStreamSynchronize(s));
+        *out_loss = hst->ortho_loss;
+    }
+done:
+    (void)hipStreamSynchronize(s);
     (void)hipFree(d);
     delete hst;
     return rc;

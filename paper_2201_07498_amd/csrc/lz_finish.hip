@@ -1,0 +1,652 @@
+// gfx950 kernels after the Lanczos loop (Sec. II, second phase): Jacobi on
+// the tridiagonal T, Top-K selection, Ritz vectors, and the accuracy report
+// of Sec. IV-D (residuals, orthogonality of the basis and of the Ritz
+// vectors, mean pairwise angle).
+#include <algorithm>
+#include <cmath>
+
+#include "lz_spmv.h"
+
+namespace lz {
+
+constexpr int JMAX_SWEEPS = 60;
+
+// ---------------------------------------------------------------- Jacobi
+// Parallel cyclic Jacobi in LDS.  Each round applies me/2 disjoint
+// rotations chosen by the round-robin tournament ordering (me = m rounded up
+// to even; an odd m gets a zero dummy row and column that is never
+// rotated); me-1 rounds make a sweep.  Rotation (Rutishauser):
+// zeta = (t_qq - t_pp)/(2 t_pq), t = sgn(zeta)/(|zeta| + sqrt(1+zeta^2)),
+// c = 1/sqrt(1+t^2), s = t c.  A rotation is skipped when |t_pq| is
+// negligible (<= eps sqrt|t_pp t_qq| or <= eps^2 ||T||_F); the method stops
+// after a sweep without rotations.
+//
+// Disjoint rotations commute, so a round is one parallel step: T' = J^T T J
+// is updated as independent 2x2 blocks (rows of pair a, columns of pair b),
+// upper blocks computed and mirrored so T stays exactly symmetric, and S' = S J.
+__device__ void jacobi_core(int m, double (*T)[MMAX + 1], double (*S)[MMAX + 1], double fro, int* sweeps_out,
+                            int* rot_flag) {
+    __shared__ double rc[MMAX / 2], rs[MMAX / 2];
+    __shared__ int rp_[MMAX / 2], rq_[MMAX / 2], rr_[MMAX / 2];
+    const double eps = 1.1102230246251565e-16;
+    const int me = (m + 1) & ~1;
+    const int half = me / 2;
+    const int nt = blockDim.x;
+    const int nblk = half * (half + 1) / 2;
+    int sweeps = -1;
+    for (int sweep = 1; sweep <= JMAX_SWEEPS; ++sweep) {
+        if (threadIdx.x == 0) *rot_flag = 0;
+        __syncthreads();
+        for (int round = 0; round < me - 1; ++round) {
+            for (int i = threadIdx.x; i < half; i += nt) {
+                auto pos = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + round) % (me - 1)); };
+                int p = pos(i), q = pos(me - 1 - i);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, s = 0.0;
+                int rot = 0;
+                const double apq = T[p][q], app = T[p][p], aqq = T[q][q];
+                if (!(fabs(apq) <= eps * sqrt(fabs(app * aqq)) || fabs(apq) <= eps * eps * fro)) {
+                    const double zeta = (aqq - app) / (2.0 * apq);
+                    double t;
+                    if (fabs(zeta) > 1e150)
+                        t = 0.5 / zeta;
+                    else
+                        t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                    rot = 1;
+                    *rot_flag = 1;
+                }
+                rc[i] = c;
+                rs[i] = s;
+                rp_[i] = p;
+                rq_[i] = q;
+                rr_[i] = rot;
+            }
+            __syncthreads();
+            // Upper 2x2 blocks (a <= b) of J^T T J, mirrored to the lower half.
+            for (int idx = threadIdx.x; idx < nblk; idx += nt) {
+                int a = 0, rem = idx;
+                while (rem >= half - a) {
+                    rem -= half - a;
+                    ++a;
+                }
+                const int b = a + rem;
+                if (!rr_[a] && !rr_[b]) continue;
+                const int pa = rp_[a], qa = rq_[a], pb = rp_[b], qb = rq_[b];
+                const double ca = rc[a], sa = rs[a], cb = rc[b], sb = rs[b];
+                const double t00 = T[pa][pb], t01 = T[pa][qb], t10 = T[qa][pb], t11 = T[qa][qb];
+                const double u00 = ca * t00 - sa * t10, u01 = ca * t01 - sa * t11;
+                const double u10 = sa * t00 + ca * t10, u11 = sa * t01 + ca * t11;
+                double v00 = cb * u00 - sb * u01, v01 = sb * u00 + cb * u01;
+                double v10 = cb * u10 - sb * u11, v11 = sb * u10 + cb * u11;
+                if (a == b) {
+                    v01 = 0.0;                  // the annihilated entry
+                    v10 = 0.0;
+                }
+                T[pa][pb] = v00;
+                T[pa][qb] = v01;
+                T[qa][pb] = v10;
+                T[qa][qb] = v11;
+                if (a != b) {
+                    T[pb][pa] = v00;
+                    T[qb][pa] = v01;
+                    T[pb][qa] = v10;
+                    T[qb][qa] = v11;
+                }
+            }
+            for (int idx = threadIdx.x; idx < me * half; idx += nt) {
+                const int r = idx / half, b = idx % half;
+                if (!rr_[b]) continue;
+                const int pb = rp_[b], qb = rq_[b];
+                const double sp = S[r][pb], sq = S[r][qb];
+                S[r][pb] = rc[b] * sp - rs[b] * sq;
+                S[r][qb] = rs[b] * sp + rc[b] * sq;
+            }
+            __syncthreads();
+        }
+        const int any = *rot_flag;
+        __syncthreads();
+        if (!any) {
+            sweeps = sweep;
+            break;
+        }
+    }
+    *sweeps_out = sweeps;
+}
+
+// T (me x me, zero-padded) from a diagonal and an off-diagonal array.
+__device__ void jacobi_load_tridiag(int m, const double* diag, const double* off, int off_shift,
+                                    double (*T)[MMAX + 1], double (*S)[MMAX + 1], double* sh, double* fro) {
+    const int me = (m + 1) & ~1;
+    double f = 0.0;
+    for (int idx = threadIdx.x; idx < me * me; idx += blockDim.x) {
+        const int r = idx / me, c = idx % me;
+        double t = 0.0;
+        if (r < m && c < m) {
+            if (r == c) t = diag[r];
+            else if (c == r + 1) t = off[r + off_shift];
+            else if (r == c + 1) t = off[c + off_shift];
+        }
+        T[r][c] = t;
+        S[r][c] = r == c ? 1.0 : 0.0;
+        f += t * t;
+    }
+    *fro = sqrt(block_sum(f, sh, blockDim.x / 64));
+    __syncthreads();
+}
+
+// T from alpha_1..alpha_m and beta_2..beta_m, Jacobi, Top-K selection by
+// modulus (ties: larger value, then lower index); writes the eigenvalues.
+__global__ __launch_bounds__(BLOCK) void k_jacobi_select(State* st, double* out_vals) {
+    __shared__ double T[MMAX][MMAX + 1];
+    __shared__ double S[MMAX][MMAX + 1];
+    __shared__ double shd[BLOCK / 64];
+    __shared__ int rot_flag, sweeps;
+    if (st->status != 0) return;
+    const int m = min(st->j, st->m);
+    const int K = st->K;
+    if (m < K) {
+        if (threadIdx.x == 0) st->status = -8;
+        return;
+    }
+    double fro;
+    jacobi_load_tridiag(m, st->alpha, st->beta, 1, T, S, shd, &fro);
+    jacobi_core(m, T, S, fro, &sweeps, &rot_flag);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) st->theta[i] = T[i][i];
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) st->S[(idx / m) * MMAX + idx % m] = S[idx / m][idx % m];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double ti = T[i][i];
+        int rank = 0;
+        for (int k = 0; k < m; ++k) {
+            const double tk = T[k][k];
+            rank += fabs(tk) > fabs(ti) || (fabs(tk) == fabs(ti) && (tk > ti || (tk == ti && k < i)));
+        }
+        if (rank < K) {
+            st->sel[rank] = i;
+            if (out_vals) out_vals[rank] = ti;
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->sweeps = sweeps;
+        if (sweeps < 0) st->status = -6;       // LZ_ERR_NOT_CONVERGED
+    }
+}
+
+// Standalone tridiagonal eigensolve (component entry point).
+__global__ __launch_bounds__(BLOCK) void k_jacobi_only(const double* alpha, const double* offd, int m, State* st) {
+    __shared__ double T[MMAX][MMAX + 1];
+    __shared__ double S[MMAX][MMAX + 1];
+    __shared__ double shd[BLOCK / 64];
+    __shared__ int rot_flag, sweeps;
+    double fro;
+    jacobi_load_tridiag(m, alpha, offd, 0, T, S, shd, &fro);
+    jacobi_core(m, T, S, fro, &sweeps, &rot_flag);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) st->theta[i] = T[i][i];
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) st->S[(idx / m) * MMAX + idx % m] = S[idx / m][idx % m];
+    if (threadIdx.x == 0) {
+        st->sweeps = sweeps;
+        st->status = sweeps < 0 ? -6 : 0;
+    }
+}
+
+// ------------------------------------------------------------ Ritz vectors
+// Y[r][k] = sum_i scale_i V[r,i] S[i, sel_k]  (eigenvectors of the matrix are
+// the Lanczos basis times those of T).  Y is row-major n x K (a K-wide row
+// per matrix row, the layout the residual SpMM gathers), not normalised.
+template <int P, int KB>
+__global__ __launch_bounds__(BLOCK) void k_ritz(const State* st, const typename Tr<P>::V* __restrict__ Vb, int64_t n,
+                                                int64_t ld, double* __restrict__ Y) {
+    __shared__ double Ss[MMAX][KB];
+    if (st->status != 0) return;
+    const int m = min(st->j, st->m), K = st->K;
+    for (int idx = threadIdx.x; idx < MMAX * KB; idx += BLOCK) {
+        const int i = idx / KB, k = idx % KB;
+        Ss[i][k] = (i < m && k < K) ? st->S[i * MMAX + st->sel[k]] * st->scale[i] : 0.0;
+    }
+    __syncthreads();
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLOCK) {
+        double acc[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) acc[k] = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double v = to_d(Vb[(int64_t)i * ld + r]);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) acc[k] += v * Ss[i][k];
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+            if (k < K) Y[r * K + k] = acc[k];
+    }
+}
+
+// Per Ritz column k: norm and the entry of largest modulus (lowest row on
+// ties) -> ysc[k] = sign(that entry) / norm.  Lane k of each group of KB2
+// lanes owns column k.
+__global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __restrict__ Y, int64_t n, int KB2,
+                                                    double* part) {
+    __shared__ double s_n[BLOCK], s_a[BLOCK], s_v[BLOCK];
+    __shared__ int64_t s_i[BLOCK];
+    __shared__ int s_last;
+    if (st->status != 0) return;
+    const int K = st->K, G = gridDim.x;
+    const int groups = BLOCK / KB2, g = threadIdx.x / KB2, k = threadIdx.x % KB2;
+    double nrm = 0.0, best = -1.0, bval = 0.0;
+    int64_t bidx = INT64_MAX;
+    if (k < K)
+        for (int64_t r = (int64_t)blockIdx.x * groups + g; r < n; r += (int64_t)G * groups) {
+            const double v = Y[r * K + k];
+            nrm += v * v;
+            const double a = fabs(v);
+            if (a > best) { best = a; bval = v; bidx = r; }
+        }
+    s_n[threadIdx.x] = nrm; s_a[threadIdx.x] = best; s_v[threadIdx.x] = bval; s_i[threadIdx.x] = bidx;
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        double tn = 0.0, ta = -1.0, tv = 0.0;
+        int64_t ti = INT64_MAX;
+        for (int gg = 0; gg < groups; ++gg) {
+            const int t = gg * KB2 + threadIdx.x;
+            tn += s_n[t];
+            if (s_a[t] > ta || (s_a[t] == ta && s_i[t] < ti)) { ta = s_a[t]; tv = s_v[t]; ti = s_i[t]; }
+        }
+        double* pb = part + ((int64_t)blockIdx.x * 64 + threadIdx.x) * 4;
+        st_dev(pb + 0, tn);
+        st_dev(pb + 1, ta);
+        st_dev(pb + 2, tv);
+        st_dev(pb + 3, (double)ti);
+    }
+    if (last_block(&st->ticket[TK_RITZ], (uint32_t)G, &s_last)) {
+        const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+        double tn = 0.0, ta = -1.0, tv = 0.0, ti = 1e300;
+        if (l < K)
+            for (int b = q; b < G; b += 4) {
+                const double* pb = part + ((int64_t)b * 64 + l) * 4;
+                tn += ld_dev(pb);
+                const double a = ld_dev(pb + 1), i = ld_dev(pb + 3);
+                if (a > ta || (a == ta && i < ti)) { ta = a; tv = ld_dev(pb + 2); ti = i; }
+            }
+        s_n[threadIdx.x] = tn; s_a[threadIdx.x] = ta; s_v[threadIdx.x] = tv; s_i[threadIdx.x] = (int64_t)ti;
+        __syncthreads();
+        if (q == 0 && l < K) {
+            double n2 = 0.0, a2 = -1.0, v2 = 0.0;
+            int64_t i2 = INT64_MAX;
+            for (int qq = 0; qq < 4; ++qq) {
+                const int t = qq * 64 + l;
+                n2 += s_n[t];
+                if (s_a[t] > a2 || (s_a[t] == a2 && s_i[t] < i2)) { a2 = s_a[t]; v2 = s_v[t]; i2 = s_i[t]; }
+            }
+            st->ysc[l] = (v2 < 0.0 ? -1.0 : 1.0) / sqrt(n2);
+        }
+    }
+}
+
+// Unit Ritz vectors into the caller's column-major output (no report).
+__global__ __launch_bounds__(BLOCK) void k_scale_out(const State* st, const double* __restrict__ Y, int64_t n,
+                                                     double* __restrict__ out) {
+    if (st->status != 0) return;
+    const int K = st->K;
+    const int64_t total = n * K;
+    for (int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * BLOCK) {
+        const int64_t k = idx / n, r = idx % n;
+        out[idx] = st->ysc[k] * Y[r * K + k];
+    }
+}
+
+// Residual check (Sec. IV-D) in FP64 for all K Ritz pairs at once:
+// D = A Y diag(ysc) - Y diag(ysc theta), the stored matrix values upcast
+// exactly.  Each work item's col/val pairs are staged in LDS once and used
+// for all K columns: lane k of a group of KB2 lanes owns pair k and gathers
+// K-wide rows of Y.  Rows of a row block are spread over groups (several
+// groups per row when the block has few rows); long-row chunks are split
+// over all groups and finished by the last chunk, as in the SpMV.  Writes
+// y_k to the output and sums d^2 per pair.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_resid_mm(State* st, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const typename Tr<P>::V* __restrict__ val,
+                                                    const double* __restrict__ Y, int64_t n, int KB2,
+                                                    const int2* __restrict__ items, const int32_t* lrow,
+                                                    const int32_t* lfirst, const int32_t* lnch, uint32_t* ltk,
+                                                    double* lpart, double* lval, double* part,
+                                                    double* __restrict__ out) {
+    __shared__ int scol[2 * NB];
+    __shared__ double sval[2 * NB];
+    __shared__ double shz[BLOCK];
+    __shared__ double red[4][64];
+    __shared__ int s_last;
+    if (st->status != 0) return;
+    const int K = st->K;
+    const int tid = threadIdx.x;
+    const int groups = BLOCK / KB2, g = tid / KB2, k = tid % KB2;
+    const bool act = k < K;
+    const double ysc = act ? st->ysc[k] : 0.0;
+    const double th = act ? st->theta[st->sel[k]] : 0.0;
+    double racc = 0.0;
+    auto finalize = [&](int64_t r, double z) -> double {
+        const double y = ysc * Y[r * K + k];
+        out[(int64_t)k * n + r] = y;
+        const double d = ysc * z - th * y;
+        return d * d;
+    };
+    const int nitems = st->n_items;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = items[it];
+        if (item.x >= 0) {
+            const int64_t rs = item.x, re = item.y;
+            const int64_t ps = rp[rs];
+            const int cnt = (int)min<int64_t>(rp[re] - ps, 2 * NB);
+            for (int t = tid; t < cnt; t += BLOCK) {
+                scol[t] = col[ps + t];
+                sval[t] = to_d(val[ps + t]);
+            }
+            __syncthreads();
+            const int nr = (int)(re - rs);
+            int gpr = 1;
+            while (gpr < groups && gpr * 2 * nr <= groups) gpr <<= 1;
+            const int per_round = groups / gpr, slot = g / gpr, sub = g % gpr;
+            for (int row0 = 0; row0 < nr; row0 += per_round) {
+                const int row = row0 + slot;
+                double z = 0.0;
+                if (row < nr && act) {
+                    const int b = (int)(rp[rs + row] - ps), e = (int)(rp[rs + row + 1] - ps);
+                    for (int p = b + sub; p < e; p += gpr) z += sval[p] * Y[(int64_t)scol[p] * K + k];
+                }
+                if (gpr > 1) {
+                    shz[tid] = z;
+                    __syncthreads();
+                    if (sub == 0) {
+                        z = 0.0;
+                        for (int s2 = 0; s2 < gpr; ++s2) z += shz[(slot * gpr + s2) * KB2 + k];
+                    }
+                    __syncthreads();
+                }
+                if (sub == 0 && row < nr && act) racc += finalize(rs + row, z);
+            }
+            __syncthreads();
+        } else {
+            const int lid = -1 - item.x;
+            const int64_t r = lrow[lid];
+            const int64_t p0 = rp[r] + (int64_t)item.y * CH;
+            const int cnt = (int)(min(p0 + (int64_t)CH, rp[r + 1]) - p0);
+            double z = 0.0;
+            for (int base = 0; base < cnt; base += 2 * NB) {
+                const int c2 = min(cnt - base, 2 * NB);
+                for (int t = tid; t < c2; t += BLOCK) {
+                    scol[t] = col[p0 + base + t];
+                    sval[t] = to_d(val[p0 + base + t]);
+                }
+                __syncthreads();
+                if (act)
+                    for (int p = g; p < c2; p += groups) z += sval[p] * Y[(int64_t)scol[p] * K + k];
+                __syncthreads();
+            }
+            shz[tid] = z;
+            __syncthreads();
+            if (g == 0 && act) {
+                double zs = 0.0;
+                for (int gg = 0; gg < groups; ++gg) zs += shz[gg * KB2 + k];
+                st_dev(&lpart[(int64_t)it * KB2 + k], zs);
+            }
+            if (last_block(&ltk[lid], (uint32_t)lnch[lid], &s_last)) {
+                if (g == 0 && act) {
+                    const int f = lfirst[lid], nc = lnch[lid];
+                    double tot = 0.0;
+                    for (int q = 0; q < nc; ++q) tot += ld_dev(&lpart[(int64_t)(f + q) * KB2 + k]);
+                    st_dev(&lval[(int64_t)lid * KB2 + k], finalize(r, tot));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    shz[tid] = racc;
+    __syncthreads();
+    if (tid < KB2) {
+        double s = 0.0;
+        for (int gg = 0; gg < groups; ++gg) s += shz[gg * KB2 + tid];
+        st_dev(&part[(int64_t)blockIdx.x * 64 + tid], s);
+    }
+    if (last_block(&st->ticket[TK_RESID], gridDim.x, &s_last)) {
+        const int nl = st->n_long, G = gridDim.x;
+        const int q = tid >> 6, l = tid & 63;
+        double s = 0.0;
+        if (l < K) {
+            for (int b = q; b < G; b += 4) s += ld_dev(&part[(int64_t)b * 64 + l]);
+            for (int i = q; i < nl; i += 4) s += ld_dev(&lval[(int64_t)i * KB2 + l]);
+        }
+        red[q][l] = s;
+        __syncthreads();
+        if (q == 0 && l < K) {
+            const double a = sqrt((red[0][l] + red[1][l]) + (red[2][l] + red[3][l]));
+            const double tl = st->theta[st->sel[l]];
+            st->abs_resid[l] = a;
+            st->resid[l] = tl != 0.0 ? a / fabs(tl) : a;
+        }
+    }
+}
+
+// -------------------------------------------------------- orthogonality
+// Gram matrix G = X^T X of c <= 64 columns (column k scaled by scale[k]) on
+// the FP64 matrix cores.  Every wavefront walks its own 16-row tiles: for
+// each group of 4 rows it loads one operand per 16-column block (lane l holds
+// X[r0 + l/16][16 b + l%16]) and issues v_mfma_f64_16x16x4f64 for every
+// upper block pair (A = 16 columns x 4 rows, B = 4 rows x 16 columns).  The
+// four wavefronts of a workgroup add their blocks in LDS in wave order; the
+// workgroup's upper blocks go to gpart[b][64][64].
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int GRT = 16;     // rows per wavefront tile
+
+template <class T, bool ROWMAJOR>
+__global__ __launch_bounds__(BLOCK) void k_gram(const State* st, const T* __restrict__ X, int64_t ldx, int64_t n,
+                                                int which, double* __restrict__ gpart) {
+    __shared__ double L[64][64];
+    if (st->status != 0) return;
+    const int c = which == 0 ? min(st->j, st->m) : st->K;
+    const double* scale = which == 0 ? st->scale : st->ysc;
+    const int nb = (c + 15) >> 4;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cl = lane & 15, rl = lane >> 4;
+    double sc[4];
+    for (int b = 0; b < 4; ++b) {
+        const int cc = b * 16 + cl;
+        sc[b] = (b < nb && cc < c) ? scale[cc] : 0.0;
+    }
+    d4 acc[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ntiles = (n + GRT - 1) / GRT;
+    const int64_t gw = (int64_t)blockIdx.x * (BLOCK / 64) + wv, nw = (int64_t)gridDim.x * (BLOCK / 64);
+    for (int64_t tile = gw; tile < ntiles; tile += nw) {
+        double x[4][4];      // [row group][column block]
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+            const int64_t r = tile * GRT + k4 * 4 + rl;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int cc = b * 16 + cl;
+                double v = 0.0;
+                if (b < nb && r < n && cc < c) v = to_d(ROWMAJOR ? X[r * ldx + cc] : X[(int64_t)cc * ldx + r]);
+                x[k4][b] = v * sc[b];
+            }
+        }
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+            int t = 0;
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = bi; bj < 4; ++bj, ++t)
+                    if (bj < nb) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[k4][bi], x[k4][bj], acc[t], 0, 0, 0);
+        }
+    }
+    // Sum the four wavefronts' blocks in LDS (wave order), then publish.
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        if (wv == w) {
+            int t = 0;
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = bi; bj < 4; ++bj, ++t)
+                    if (bj < nb)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            // Accumulator element e of lane l holds D[4e + l/16][l % 16].
+                            const int i = bi * 16 + e * 4 + rl, jj = bj * 16 + cl;
+                            L[i][jj] = (w == 0 ? 0.0 : L[i][jj]) + acc[t][e];
+                        }
+        }
+        __syncthreads();
+    }
+    double* g = gpart + (int64_t)blockIdx.x * 64 * 64;
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += BLOCK) {
+        const int i = idx / 64, jj = idx % 64;
+        if ((i >> 4) <= (jj >> 4) && (jj >> 4) < nb) g[idx] = L[i][jj];
+    }
+}
+
+// G[i][j] = sum over workgroups of the upper blocks, symmetrised.
+__global__ __launch_bounds__(BLOCK) void k_gram_reduce(const State* st, const double* gpart, int nparts, int which,
+                                                       double* G) {
+    const int c = which == 0 ? min(st->j, st->m) : st->K;
+    const int idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= 64 * 64) return;
+    const int i = idx / 64, jj = idx % 64;
+    if (i >= c || jj >= c) return;
+    const int lo = min(i, jj), hi = max(i, jj);
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += gpart[(int64_t)b * 4096 + lo * 64 + hi];
+    G[i * 64 + jj] = s;
+}
+
+// max |G - I| and, for the Ritz vectors, the mean angle between pairs.
+__global__ __launch_bounds__(BLOCK) void k_gram_metrics(State* st, const double* G, int which) {
+    __shared__ double shd[BLOCK / 64];
+    __shared__ double shm[BLOCK];
+    if (st->status != 0) return;
+    const int c = which == 0 ? min(st->j, st->m) : st->K;
+    double worst = 0.0, ang = 0.0;
+    for (int idx = threadIdx.x; idx < c * c; idx += BLOCK) {
+        const int i = idx / c, jj = idx % c;
+        const double g = G[i * 64 + jj];
+        worst = fmax(worst, fabs(g - (i == jj ? 1.0 : 0.0)));
+        if (i < jj) ang += acos(fmin(1.0, fabs(g))) * (180.0 / 3.14159265358979323846);
+    }
+    shm[threadIdx.x] = worst;
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    ang = block_sum(ang, shd);
+    if (threadIdx.x == 0) {
+        if (which == 0) {
+            st->ortho_loss = shm[0];
+        } else {
+            st->ritz_ortho_loss = shm[0];
+            st->mean_angle_deg = c > 1 ? ang / (0.5 * c * (c - 1)) : 90.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static int pow2_at_least(int k) {
+    int v = 1;
+    while (v < k) v <<= 1;
+    return v;
+}
+
+static int gram_grid(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_PARTS, (n + 4 * GRT - 1) / (4 * GRT)));
+}
+
+template <int P>
+static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* out_vals, double* out_vecs,
+                           int report, hipStream_t s) {
+    using VT = typename Tr<P>::V;
+    const VT* V = (const VT*)b.V;
+    hipLaunchKernelGGL(k_jacobi_select, dim3(1), dim3(BLOCK), 0, s, b.st, out_vals);
+    switch (p.KB) {
+#define LZ_RITZ_CASE(KBV)                                                                                    \
+    case KBV:                                                                                                \
+        hipLaunchKernelGGL((k_ritz<P, KBV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, p.n, p.ld, b.Y);  \
+        break;
+        LZ_RITZ_CASE(8)
+        LZ_RITZ_CASE(16)
+        LZ_RITZ_CASE(24)
+        LZ_RITZ_CASE(32)
+        LZ_RITZ_CASE(40)
+        LZ_RITZ_CASE(48)
+        LZ_RITZ_CASE(56)
+        LZ_RITZ_CASE(64)
+#undef LZ_RITZ_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    const int kb2 = pow2_at_least(p.K);
+    const int gc = (int)std::max<int64_t>(1, std::min<int64_t>(256, (p.n * kb2 + BLOCK - 1) / BLOCK));
+    hipLaunchKernelGGL(k_colstats, dim3(gc), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, b.part);
+    if (!report) {
+        const int go = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (p.n * p.K + BLOCK - 1) / BLOCK));
+        hipLaunchKernelGGL(k_scale_out, dim3(go), dim3(BLOCK), 0, s, b.st, b.Y, p.n, out_vecs);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_resid_mm<P>), dim3(p.g_spmv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, (const VT*)a.val,
+                       b.Y, p.n, kb2, b.items, b.lrow, b.lfirst, b.lnch, b.ltk, b.lpart, b.lval, b.part2, out_vecs);
+    const int gg = gram_grid(p.n);
+    double* G = b.gram + (int64_t)GRAM_PARTS * 4096;
+    hipLaunchKernelGGL((k_gram<VT, false>), dim3(gg), dim3(BLOCK), 0, s, b.st, V, p.ld, p.n, 0, b.gram);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(16), dim3(BLOCK), 0, s, b.st, b.gram, gg, 0, G);
+    hipLaunchKernelGGL(k_gram_metrics, dim3(1), dim3(BLOCK), 0, s, b.st, G, 0);
+    hipLaunchKernelGGL((k_gram<double, true>), dim3(gg), dim3(BLOCK), 0, s, b.st, b.Y, (int64_t)p.K, p.n, 1, b.gram);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(16), dim3(BLOCK), 0, s, b.st, b.gram, gg, 1, G);
+    hipLaunchKernelGGL(k_gram_metrics, dim3(1), dim3(BLOCK), 0, s, b.st, G, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals, double* out_vecs, int report,
+                         hipStream_t s) {
+    switch (p.prec) {
+        case 0: return finish_p<0>(p, b, a, out_vals, out_vecs, report, s);
+        case 1: return finish_p<1>(p, b, a, out_vals, out_vecs, report, s);
+        case 2: return finish_p<2>(p, b, a, out_vals, out_vecs, report, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gram_only(int prec, const void* X, int64_t ldx, int64_t n, State* st, double* gram,
+                            hipStream_t s) {
+    const int gg = gram_grid(n);
+    double* G = gram + (int64_t)GRAM_PARTS * 4096;
+    switch (prec) {
+        case 0:
+            hipLaunchKernelGGL((k_gram<double, false>), dim3(gg), dim3(BLOCK), 0, s, st, (const double*)X, ldx, n, 0,
+                               gram);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_gram<float, false>), dim3(gg), dim3(BLOCK), 0, s, st, (const float*)X, ldx, n, 0,
+                               gram);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_gram<uint16_t, false>), dim3(gg), dim3(BLOCK), 0, s, st, (const uint16_t*)X, ldx,
+                               n, 0, gram);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_gram_reduce, dim3(16), dim3(BLOCK), 0, s, st, gram, gg, 0, G);
+    hipLaunchKernelGGL(k_gram_metrics, dim3(1), dim3(BLOCK), 0, s, st, G, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_only(const double* alpha, const double* offdiag, int m, State* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_jacobi_only, dim3(1), dim3(BLOCK), 0, s, alpha, offdiag, m, st);
+    return hipGetLastError();
+}
+
+}  // namespace lz

@@ -19,6 +19,7 @@ constexpr int RMAX = 256;      // rows per row-block work item at most
 constexpr int LDPAD = 2048;    // basis leading dimension is a multiple of this
 constexpr int OGRID = 1024;    // orthogonalisation grid cap (workgroups)
 constexpr int SGRID = 2048;    // SpMV grid cap (workgroups)
+constexpr int GRAM_PARTS = 256; // Gram kernel grid cap (per-workgroup 64x64 partials)
 
 enum Mode { MODE_NORMAL = 0, MODE_RESTART = 1 };
 
@@ -79,7 +80,7 @@ struct Bufs {
     State* st;
     void* V;
     void* w;
-    double* part;      // per-workgroup partial sums (g_orth * NCMAX or g_spmv)
+    double* part;      // per-workgroup partials: max(g_orth, 256) * 256 doubles
     double* part2;     // second partial buffer (SpMV long rows, residual)
     int2* items;
     int32_t* lrow;
@@ -90,8 +91,8 @@ struct Bufs {
     double* lval;      // per-long-row epilogue values (long_cap * KB)
     uint64_t* scan;
     uint64_t* bsum;
-    double* Y;         // Ritz vectors, row-major n x K
-    double* gram;      // Gram partials
+    double* Y;         // Ritz vectors, column-major n x K, before normalisation
+    double* gram;      // Gram partials (GRAM_PARTS x 64 x 64), then the reduced 64 x 64
 };
 Bufs resolve(const Plan& p, void* base);
 
@@ -109,13 +110,19 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
 hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s);
 // One Lanczos iteration (SpMV or restart draw, two CGS passes, store).
 // `ncols_bound` >= j+1 for every j the iteration can see.
+// With `ev` non-null, ev[0] is recorded before the SpMV, ev[1] after it and
+// ev[2] after the reorthogonalisation kernels.
 hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols_bound,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
                          double* out_vecs, int report, hipStream_t s);
 hipError_t launch_spmv_plain(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y,
                              hipStream_t s);
 hipError_t launch_jacobi_only(const double* alpha, const double* offdiag, int m, State* st,
                               hipStream_t s);
+// max |X^T X - I| of the first st->j columns of X (scales st->scale) into
+// st->ortho_loss, with the kernels of the solve report.
+hipError_t launch_gram_only(int prec, const void* X, int64_t ldx, int64_t n, State* st, double* gram,
+                            hipStream_t s);
 
 }  // namespace lz

@@ -175,3 +175,31 @@ def test_plain_entry_point_matches_ex():
     vals2, vecs2, _ = lz.topk(drp, dc, dv, 4, 12, "fp64")
     torch.cuda.synchronize()
     assert torch.equal(vals, vals2) and torch.equal(vecs, vecs2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,c", [(1, 1), (300, 5), (1000, 16), (999, 17), (4133, 48), (2048, 64)])
+def test_gram_orthogonality_loss_matches_numpy(n, c, precision):
+    # MFMA f64 Gram kernel of the report: max |X^T X - I| for a perturbed
+    # orthonormal X with a known, non-trivial loss pattern.
+    rng = np.random.default_rng(n + c)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, c))) if n >= c else (np.ones((1, 1)), None)
+    X = Q @ (np.eye(c) + 1e-2 * np.triu(rng.standard_normal((c, c))))
+    X = synth.round_values(X, precision).reshape(n, c)
+    want = np.max(np.abs(X.T @ X - np.eye(c)))
+    dX = device_values(X.T.copy().ravel(), precision).view(c, n).T    # column-major n x c
+    got = lz.ortho_loss(dX, precision)
+    assert abs(got - want) <= 1e-12 * max(1.0, want), (got, want)
+
+
+def test_report_metrics_match_oracle_definitions():
+    rp, c, v = synth.er(6000, 9.0, seed=5)
+    K, m = 6, 30
+    vals, Y, rep = run_gpu(rp, c, v, K, m, "fp64", seed=5)
+    ref = oracle.topk(rp, c, v, K, m, seed=5)
+    assert rep["ortho_loss"] < 1e-13 and ref["ortho_loss"] < 1e-13
+    assert abs(rep["ritz_ortho_loss"] - oracle.ortho_loss(Y)) < 1e-13
+    assert abs(rep["mean_angle_deg"] - oracle.mean_angle_deg(Y)) < 1e-9
+    ab, rel = oracle.residuals(rp, c, v, vals, Y)
+    np.testing.assert_allclose(rep["abs_resid"], ab, rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(rep["resid"], rel, rtol=1e-9, atol=1e-14)
