@@ -81,6 +81,135 @@ def run_mode(lz, dev_csr, K, m, precision, steps, warmup, ws):
                 vecs=out[1].T.cpu().numpy())
 
 
+# ------------------------------------------------------------------ serving
+def serving_pool(n_pool: int, seed: int = 0):
+    """Distinct matrices of the request stream: n log-uniform in [1e4, 2e6],
+    average degree U[4, 32], R-MAT or ER, weights U(0,1)."""
+    import synth
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(n_pool):
+        n = int(10 ** rng.uniform(4.0, np.log10(2e6)))
+        d = float(rng.uniform(4, 32))
+        if rng.random() < 0.5:
+            rp, c, v = synth.rmat_n(n, d, seed=seed * 1000 + i)
+            kind = "rmat"
+        else:
+            rp, c, v = synth.er(n, d - 1.0, seed=seed * 1000 + i)
+            v = np.abs(v)
+            kind = "er"
+        v = synth.round_values(v, "fp32")      # FP32 and FP64 requests see one matrix
+        pool.append(dict(rp=rp, col=c, val=v, n=n, nnz=int(rp[-1]), kind=kind))
+    return pool
+
+
+def pinned(a):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.pin_memory()
+
+
+def serving_requests(pool, n_req: int, seed: int = 1):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        K = int(rng.choice([4, 8, 16]))
+        reqs.append(dict(pool=int(rng.integers(len(pool))), K=K, m=3 * K,
+                         prec=str(rng.choice(["fp64", "fp32", "bf16"])), seed=i))
+    return reqs
+
+
+def run_stream(lz, pool_dev, reqs, arrivals, force_prec, budget, slots):
+    """Submits requests at their arrival times (seconds from start) and waits
+    for all.  Returns (elapsed_s, latencies_ms, results by index)."""
+    srv = lz.Server(budget, max_slots=slots, use_graphs=True)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for q, ta in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            p = force_prec or q["prec"]
+            src = pool_dev[q["pool"]]
+            tickets.append(srv.submit(src["rp"], src["col"], src[p], q["K"], q["m"], p, seed=q["seed"]))
+        out = []
+        for t in tickets:
+            vals, _, res = srv.wait(t)
+            out.append((vals.copy(), res))
+            srv.release(t)
+        elapsed = time.perf_counter() - t0
+        stats = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for _, r in out])
+    return elapsed, lat, out, stats
+
+
+def serving_main(args):
+    import synth
+    import paper_2201_07498_amd as lz
+    t = time.perf_counter()
+    pool = serving_pool(args.pool)
+    pool_dev = []
+    for m_ in pool:
+        d = dict(rp=pinned(m_["rp"]), col=pinned(m_["col"]))
+        for p in ("fp64", "fp32", "bf16"):
+            d[p] = pinned(synth.to_storage(m_["val"], p).view(np.int16) if p == "bf16"
+                          else synth.to_storage(m_["val"], p))
+        pool_dev.append(d)
+    reqs = serving_requests(pool, args.requests)
+    print(f"[serving] pool of {len(pool)} matrices (n {min(p['n'] for p in pool)}..{max(p['n'] for p in pool)}), "
+          f"{len(reqs)} requests, prepared in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+    budget = int(args.budget_gb * (1 << 30))
+    burst = np.zeros(len(reqs))
+    runs = {}
+    for name, force in (("fp64", "fp64"), ("fp32", "fp32"), ("mix", None)):
+        el, lat, out, st = run_stream(lz, pool_dev, reqs, burst, force, budget, args.slots)
+        runs[name] = dict(elapsed=el, lat=lat, out=out, stats=st)
+        print(f"[serving] saturation {name}: {len(reqs) / el:.1f} solves/s, p50 {np.percentile(lat, 50):.1f} ms, "
+              f"p99 {np.percentile(lat, 99):.1f} ms, arena peak {st['arena_peak'] / 2**30:.1f} GiB",
+              file=sys.stderr, flush=True)
+    cap = len(reqs) / runs["fp64"]["elapsed"]
+    rate = 0.8 * cap
+    arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, len(reqs)))
+    el, lat, out, st = run_stream(lz, pool_dev, reqs, arr, None, budget, args.slots)
+    print(f"[serving] poisson mix at {rate:.1f} req/s: p50 {np.percentile(lat, 50):.1f} ms, "
+          f"p99 {np.percentile(lat, 99):.1f} ms", file=sys.stderr, flush=True)
+    err = []
+    for (v32, _), (v64, _) in zip(runs["fp32"]["out"], runs["fp64"]["out"]):
+        den = np.maximum(np.abs(v64), 1e-12 * np.max(np.abs(v64)))
+        err.append(float(np.max(np.abs(v32 - v64) / den)))
+    err = np.array(err)
+    f = lambda r: {"solves_per_s": len(reqs) / r["elapsed"],
+                   "latency_ms": {"p50": float(np.percentile(r["lat"], 50)),
+                                  "p99": float(np.percentile(r["lat"], 99))}}
+    line = {
+        "metric": METRIC,
+        "value": len(reqs) / runs["fp32"]["elapsed"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": runs["fp32"]["elapsed"] / len(reqs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving", "description": "request stream: R-MAT/ER, n log-uniform in [1e4, 2e6], "
+                   "degree U[4,32], K in {4,8,16}, m=3K", "requests": len(reqs), "pool": len(pool),
+                   "slots": args.slots, "budget_gb": args.budget_gb, "parallelism": "single-gpu"},
+        "fp32": f(runs["fp32"]), "fp64": f(runs["fp64"]), "mix": f(runs["mix"]),
+        "poisson_mix": {"rate_per_s": rate, "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                                            "p99": float(np.percentile(lat, 99))}},
+        "speedup_fp32_vs_fp64": runs["fp64"]["elapsed"] / runs["fp32"]["elapsed"],
+        "eig_rel_err_fp32_vs_fp64": {"max": float(err.max()), "median": float(np.median(err))},
+        "arena_peak_gib": runs["mix"]["stats"]["arena_peak"] / 2 ** 30,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,12 +217,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
+    ap.add_argument("--pool", type=int, default=16, help="serving: distinct matrices")
+    ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM arena")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "row-partitioned path is a design, not built", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serving":
+        return serving_main(args)
     import torch
     import paper_2201_07498_amd as lz
     sys.path.insert(0, os.path.join(ROOT, "tests"))

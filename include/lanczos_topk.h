@@ -167,6 +167,69 @@ int lz_tridiag_eig(const double* alpha, const double* offdiag, int32_t m,
 int lz_ortho_loss(const void* X, int64_t ldx, int64_t n, int32_t c, int32_t precision, void* stream,
                   double* out_loss);
 
+/* ------------------------------------------------------------------ */
+/* Serving: a request loop that admits Top-K solves as they arrive, keeps
+ * each admitted request's CSR and Lanczos state resident in a fixed HBM
+ * arena, and runs admitted requests concurrently on their own HIP streams
+ * (continuous batching).  A request is admitted when a slot is free and its
+ * footprint (CSR + workspace + outputs) fits in the arena; the queue is FIFO
+ * with bounded backfill.  Results do not depend on what else is running:
+ * every kernel's launch shape depends only on the request itself.  All
+ * pointers in lz_request are HOST pointers owned by the caller and must stay
+ * valid until the request has completed (pinned memory copies faster). */
+typedef struct lz_server lz_server;
+
+typedef struct lz_request {
+    const int64_t* rowptr;   /* host int64[n+1] */
+    const int32_t* col;      /* host int32[nnz] */
+    const void* val;         /* host values in the storage precision */
+    int64_t n, nnz;
+    int32_t K, m, precision, reorth;   /* reorth: LZ_REORTH_* */
+    uint64_t seed;
+    double* out_vals;        /* host double[K], written on completion */
+    double* out_vecs;        /* host double[n*K] column-major, or NULL */
+} lz_request;
+
+typedef struct lz_result {
+    int32_t status;          /* lz_status of the solve */
+    int32_t m_eff, restarts, slot;
+    double t_submit_ms;      /* host steady clock, ms since server creation */
+    double t_admit_ms;
+    double t_done_ms;        /* when the server observed completion */
+    double device_ms;        /* first copy to last kernel, on the device */
+    double resid_max;        /* max relative residual over the K pairs */
+    double ortho_loss;       /* max |V^T V - I| of the basis */
+} lz_result;
+
+typedef struct lz_server_stats {
+    uint64_t submitted, completed, rejected, active, queued;
+    size_t arena_bytes, arena_in_use, arena_peak;
+} lz_server_stats;
+
+/* Creates a server on `device` with an HBM arena of hbm_budget_bytes and at
+ * most max_slots requests in flight; use_graphs = 1 captures each request's
+ * Lanczos iterations in a hipGraph. */
+int lz_server_create(int device, size_t hbm_budget_bytes, int32_t max_slots, int32_t use_graphs,
+                     lz_server** out);
+
+/* Device bytes a request occupies while admitted (0 for invalid shapes). */
+size_t lz_request_footprint(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision);
+
+/* Queues a request; returns LZ_ERR_TOO_LARGE if it can never fit. */
+int lz_server_submit(lz_server* s, const lz_request* req, uint64_t* ticket);
+
+/* LZ_PENDING while the request runs; otherwise its final status, with *res
+ * filled (res may be NULL).  A finished ticket can be polled again. */
+int lz_server_poll(lz_server* s, uint64_t ticket, lz_result* res);
+
+/* Blocks until the request has finished; returns its status. */
+int lz_server_wait(lz_server* s, uint64_t ticket, lz_result* res);
+
+int lz_server_get_stats(lz_server* s, lz_server_stats* out);
+
+/* Waits for every request, stops the worker and frees the arena. */
+int lz_server_destroy(lz_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -208,3 +208,139 @@ def ortho_loss(X, precision="fp64", stream=None) -> float:
     if rc != 0:
         raise LanczosError(rc, "lz_ortho_loss")
     return out.value
+
+
+# ------------------------------------------------------------------ serving
+class Request(ctypes.Structure):
+    _fields_ = [("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("K", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reorth", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("out_vals", ctypes.c_void_p), ("out_vecs", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("m_eff", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("slot", ctypes.c_int32), ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double), ("resid_max", ctypes.c_double),
+                ("ortho_loss", ctypes.c_double)]
+
+    def to_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("active", ctypes.c_uint64), ("queued", ctypes.c_uint64), ("arena_bytes", ctypes.c_size_t),
+                ("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+
+
+def _server_lib():
+    L = lib()
+    if not hasattr(L, "_server_ready"):
+        P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.lz_request_footprint.restype = ctypes.c_size_t
+        L.lz_request_footprint.argtypes = [i64, i64, i32, i32, i32]
+        L.lz_server_create.restype = ctypes.c_int
+        L.lz_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, i32, i32, ctypes.POINTER(P)]
+        L.lz_server_submit.restype = ctypes.c_int
+        L.lz_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.lz_server_poll.restype = ctypes.c_int
+        L.lz_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+        L.lz_server_wait.restype = ctypes.c_int
+        L.lz_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+        L.lz_server_get_stats.restype = ctypes.c_int
+        L.lz_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+        L.lz_server_destroy.restype = ctypes.c_int
+        L.lz_server_destroy.argtypes = [P]
+        L._server_ready = True
+    return L
+
+
+def request_footprint(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
+    return int(_server_lib().lz_request_footprint(n, nnz, K, m, _prec(precision)))
+
+
+def _host_ptr(a):
+    """Address of a contiguous host array (numpy array or CPU torch tensor)."""
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise TypeError("host arrays must be contiguous")
+        return a.ctypes.data
+    if a.is_cuda or not a.is_contiguous():
+        raise TypeError("host arrays must be contiguous CPU tensors")
+    return a.data_ptr()
+
+
+class Server:
+    """Continuous-batching request loop of the C library (lz_server_*).
+
+    submit() takes host CSR arrays (numpy or pinned CPU tensors); they and
+    the output buffers are kept alive here until the request completes."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, use_graphs: bool = True, device: int = 0):
+        L = _server_lib()
+        h = ctypes.c_void_p()
+        rc = L.lz_server_create(device, int(hbm_budget_bytes), max_slots, 1 if use_graphs else 0, ctypes.byref(h))
+        if rc != 0:
+            raise LanczosError(rc, "lz_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
+               want_vectors: bool = False) -> int:
+        n = len(rowptr) - 1
+        nnz = len(col)
+        vals = np.zeros(K, dtype=np.float64)
+        vecs = np.zeros((K, n), dtype=np.float64) if want_vectors else None
+        req = Request(rowptr=_host_ptr(rowptr), col=_host_ptr(col), val=_host_ptr(val), n=n, nnz=nnz, K=K, m=m,
+                      precision=_prec(precision), reorth=REORTH[reorth] if isinstance(reorth, str) else int(reorth),
+                      seed=seed & (2 ** 64 - 1), out_vals=vals.ctypes.data,
+                      out_vecs=vecs.ctypes.data if vecs is not None else None)
+        t = ctypes.c_uint64(0)
+        rc = _server_lib().lz_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if rc != 0:
+            raise LanczosError(rc, "lz_server_submit")
+        self._keep[t.value] = (rowptr, col, val, vals, vecs)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running, else (vals, vecs or None, result dict)."""
+        res = Result()
+        rc = _server_lib().lz_server_poll(self._h, ticket, ctypes.byref(res))
+        if rc == 1:
+            return None
+        return self._finish(ticket, rc, res)
+
+    def wait(self, ticket: int):
+        res = Result()
+        rc = _server_lib().lz_server_wait(self._h, ticket, ctypes.byref(res))
+        return self._finish(ticket, rc, res)
+
+    def _finish(self, ticket, rc, res):
+        keep = self._keep.get(ticket)
+        if rc < 0 and keep is None:
+            raise LanczosError(rc, "lz_server_poll")
+        d = res.to_dict()
+        d["status"] = rc
+        vals, vecs = (keep[3], keep[4]) if keep else (None, None)
+        return vals, (vecs.T if vecs is not None else None), d
+
+    def release(self, ticket: int):
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _server_lib().lz_server_get_stats(self._h, ctypes.byref(st))
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
+    def close(self):
+        if self._h:
+            _server_lib().lz_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -30,7 +30,7 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.items_cap = ceil_div(n, RMAX) + 3 * ceil_div(nnz, NB) + ceil_div(nnz, CH) + 2;
     p.long_cap = nnz / NB + 1;
     const int64_t est_items = ceil_div(nnz, NB) + ceil_div(n, RMAX);
-    p.g_spmv = (int32_t)std::max<int64_t>(1, std::min<int64_t>(SGRID, est_items));
+    p.g_spmv = (int32_t)std::max<int64_t>(1, std::min<int64_t>(SGRID, ceil_div(est_items, 4)));
     const int kb2 = pow2_ge(K);
     const size_t vb = storage_bytes(prec), wb = work_bytes(prec);
     size_t o = 0;

@@ -10,6 +10,7 @@
 namespace lz {
 
 constexpr int JMAX_SWEEPS = 60;
+constexpr int JBLOCK = 1024;      // Jacobi workgroup: one round is a single parallel step
 
 // ---------------------------------------------------------------- Jacobi
 // Parallel cyclic Jacobi in LDS.  Each round applies me/2 disjoint
@@ -28,24 +29,36 @@ __device__ void jacobi_core(int m, double (*T)[MMAX + 1], double (*S)[MMAX + 1],
                             int* rot_flag) {
     __shared__ double rc[MMAX / 2], rs[MMAX / 2];
     __shared__ int rp_[MMAX / 2], rq_[MMAX / 2], rr_[MMAX / 2];
+    __shared__ uint8_t pair_p[MMAX - 1][MMAX / 2], pair_q[MMAX - 1][MMAX / 2];
+    __shared__ uint8_t blk_a[MMAX / 2 * (MMAX / 2 + 1) / 2], blk_b[MMAX / 2 * (MMAX / 2 + 1) / 2];
     const double eps = 1.1102230246251565e-16;
     const int me = (m + 1) & ~1;
     const int half = me / 2;
     const int nt = blockDim.x;
     const int nblk = half * (half + 1) / 2;
+    // Tournament pairs of every round and the upper 2x2 block list, once.
+    for (int idx = threadIdx.x; idx < (me - 1) * half; idx += nt) {
+        const int round = idx / half, i = idx % half;
+        auto pos = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + round) % (me - 1)); };
+        const int p = pos(i), q = pos(me - 1 - i);
+        pair_p[round][i] = (uint8_t)min(p, q);
+        pair_q[round][i] = (uint8_t)max(p, q);
+    }
+    for (int a = threadIdx.x; a < half; a += nt) {
+        const int first = a * half - a * (a - 1) / 2;      // blocks (a', b) with a' < a come first
+        for (int b = a; b < half; ++b) {
+            blk_a[first + b - a] = (uint8_t)a;
+            blk_b[first + b - a] = (uint8_t)b;
+        }
+    }
+    __syncthreads();
     int sweeps = -1;
     for (int sweep = 1; sweep <= JMAX_SWEEPS; ++sweep) {
         if (threadIdx.x == 0) *rot_flag = 0;
         __syncthreads();
         for (int round = 0; round < me - 1; ++round) {
             for (int i = threadIdx.x; i < half; i += nt) {
-                auto pos = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + round) % (me - 1)); };
-                int p = pos(i), q = pos(me - 1 - i);
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
+                const int p = pair_p[round][i], q = pair_q[round][i];
                 double c = 1.0, s = 0.0;
                 int rot = 0;
                 const double apq = T[p][q], app = T[p][p], aqq = T[q][q];
@@ -70,12 +83,7 @@ __device__ void jacobi_core(int m, double (*T)[MMAX + 1], double (*S)[MMAX + 1],
             __syncthreads();
             // Upper 2x2 blocks (a <= b) of J^T T J, mirrored to the lower half.
             for (int idx = threadIdx.x; idx < nblk; idx += nt) {
-                int a = 0, rem = idx;
-                while (rem >= half - a) {
-                    rem -= half - a;
-                    ++a;
-                }
-                const int b = a + rem;
+                const int a = blk_a[idx], b = blk_b[idx];
                 if (!rr_[a] && !rr_[b]) continue;
                 const int pa = rp_[a], qa = rq_[a], pb = rp_[b], qb = rq_[b];
                 const double ca = rc[a], sa = rs[a], cb = rc[b], sb = rs[b];
@@ -100,7 +108,7 @@ __device__ void jacobi_core(int m, double (*T)[MMAX + 1], double (*S)[MMAX + 1],
                 }
             }
             for (int idx = threadIdx.x; idx < me * half; idx += nt) {
-                const int r = idx / half, b = idx % half;
+                const int r = idx / half, b = idx - r * half;
                 if (!rr_[b]) continue;
                 const int pb = rp_[b], qb = rq_[b];
                 const double sp = S[r][pb], sq = S[r][qb];
@@ -142,10 +150,10 @@ __device__ void jacobi_load_tridiag(int m, const double* diag, const double* off
 
 // T from alpha_1..alpha_m and beta_2..beta_m, Jacobi, Top-K selection by
 // modulus (ties: larger value, then lower index); writes the eigenvalues.
-__global__ __launch_bounds__(BLOCK) void k_jacobi_select(State* st, double* out_vals) {
+__global__ __launch_bounds__(JBLOCK) void k_jacobi_select(State* st, double* out_vals) {
     __shared__ double T[MMAX][MMAX + 1];
     __shared__ double S[MMAX][MMAX + 1];
-    __shared__ double shd[BLOCK / 64];
+    __shared__ double shd[JBLOCK / 64];
     __shared__ int rot_flag, sweeps;
     if (st->status != 0) return;
     const int m = min(st->j, st->m);
@@ -179,10 +187,10 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_select(State* st, double* out_
 }
 
 // Standalone tridiagonal eigensolve (component entry point).
-__global__ __launch_bounds__(BLOCK) void k_jacobi_only(const double* alpha, const double* offd, int m, State* st) {
+__global__ __launch_bounds__(JBLOCK) void k_jacobi_only(const double* alpha, const double* offd, int m, State* st) {
     __shared__ double T[MMAX][MMAX + 1];
     __shared__ double S[MMAX][MMAX + 1];
-    __shared__ double shd[BLOCK / 64];
+    __shared__ double shd[JBLOCK / 64];
     __shared__ int rot_flag, sweeps;
     double fro;
     jacobi_load_tridiag(m, alpha, offd, 0, T, S, shd, &fro);
@@ -307,6 +315,26 @@ __global__ __launch_bounds__(BLOCK) void k_scale_out(const State* st, const doub
 // groups per row when the block has few rows); long-row chunks are split
 // over all groups and finished by the last chunk, as in the SpMV.  Writes
 // y_k to the output and sums d^2 per pair.
+// sum over p = p0, p0+step, ... < e of sval[p] * Y[scol[p]][k], with four
+// gathers in flight per lane (fixed association order).
+__device__ __forceinline__ double gather_dot(const int* scol, const double* sval, int p0, int e, int step,
+                                             const double* __restrict__ Y, int K, int k) {
+    double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+    int p = p0;
+    for (; p + 3 * step < e; p += 4 * step) {
+        const double y0 = Y[(int64_t)scol[p] * K + k];
+        const double y1 = Y[(int64_t)scol[p + step] * K + k];
+        const double y2 = Y[(int64_t)scol[p + 2 * step] * K + k];
+        const double y3 = Y[(int64_t)scol[p + 3 * step] * K + k];
+        z0 += sval[p] * y0;
+        z1 += sval[p + step] * y1;
+        z2 += sval[p + 2 * step] * y2;
+        z3 += sval[p + 3 * step] * y3;
+    }
+    for (; p < e; p += step) z0 += sval[p] * Y[(int64_t)scol[p] * K + k];
+    return (z0 + z1) + (z2 + z3);
+}
+
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_resid_mm(State* st, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ col,
@@ -356,7 +384,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid_mm(State* st, const int64_t* __
                 double z = 0.0;
                 if (row < nr && act) {
                     const int b = (int)(rp[rs + row] - ps), e = (int)(rp[rs + row + 1] - ps);
-                    for (int p = b + sub; p < e; p += gpr) z += sval[p] * Y[(int64_t)scol[p] * K + k];
+                    z = gather_dot(scol, sval, b + sub, e, gpr, Y, K, k);
                 }
                 if (gpr > 1) {
                     shz[tid] = z;
@@ -383,8 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid_mm(State* st, const int64_t* __
                     sval[t] = to_d(val[p0 + base + t]);
                 }
                 __syncthreads();
-                if (act)
-                    for (int p = g; p < c2; p += groups) z += sval[p] * Y[(int64_t)scol[p] * K + k];
+                if (act) z += gather_dot(scol, sval, g, c2, groups, Y, K, k);
                 __syncthreads();
             }
             shz[tid] = z;
@@ -570,7 +597,7 @@ static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* o
                            int report, hipStream_t s) {
     using VT = typename Tr<P>::V;
     const VT* V = (const VT*)b.V;
-    hipLaunchKernelGGL(k_jacobi_select, dim3(1), dim3(BLOCK), 0, s, b.st, out_vals);
+    hipLaunchKernelGGL(k_jacobi_select, dim3(1), dim3(JBLOCK), 0, s, b.st, out_vals);
     switch (p.KB) {
 #define LZ_RITZ_CASE(KBV)                                                                                    \
     case KBV:                                                                                                \
@@ -645,7 +672,7 @@ hipError_t launch_gram_only(int prec, const void* X, int64_t ldx, int64_t n, Sta
 }
 
 hipError_t launch_jacobi_only(const double* alpha, const double* offdiag, int m, State* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_jacobi_only, dim3(1), dim3(BLOCK), 0, s, alpha, offdiag, m, st);
+    hipLaunchKernelGGL(k_jacobi_only, dim3(1), dim3(JBLOCK), 0, s, alpha, offdiag, m, st);
     return hipGetLastError();
 }
 

@@ -13,9 +13,9 @@ namespace lz {
 constexpr int MMAX = 64;       // largest m (Lanczos steps); Jacobi tile in LDS
 constexpr int NCMAX = 72;      // column bound of the orthogonalisation kernels (m+1 rounded to 8)
 constexpr int BLOCK = 256;     // threads per workgroup (4 wave64)
-constexpr int NB = 1024;       // target non-zeros per row-block work item
-constexpr int CH = 4096;       // non-zeros per chunk of a long row
-constexpr int RMAX = 256;      // rows per row-block work item at most
+constexpr int NB = 256;        // target non-zeros per row-block work item (one wavefront)
+constexpr int CH = 2048;       // non-zeros per chunk of a long row
+constexpr int RMAX = 64;       // rows per row-block work item at most
 constexpr int LDPAD = 2048;    // basis leading dimension is a multiple of this
 constexpr int OGRID = 1024;    // orthogonalisation grid cap (workgroups)
 constexpr int SGRID = 2048;    // SpMV grid cap (workgroups)

@@ -270,8 +270,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const int64_t* _
     const double sj = st->scale[j];
     const double bsc = j > 0 ? st->beta[j] * st->scale[j - 1] : 0.0;
     double apart = 0.0;
-    spmv_items<VT, VT, AT>(st, rp, col, val, x, st->n_items, items, lrow, lfirst, lnch, ltk, lpart, blockIdx.x,
-                           gridDim.x, [&](int64_t r, double acc, bool is_long, int lid) {
+    spmv_items<VT, VT, AT>(st, rp, col, val, x, st->n_items, items, lrow, lfirst, lnch, ltk, lpart,
+                           blockIdx.x * WAVES + (threadIdx.x >> 6), gridDim.x * WAVES,
+                           [&](int64_t r, double acc, bool is_long, int lid) {
                                const double y = sj * acc;
                                const double a = sj * to_d(x[r]) * y;
                                const double wp = xp ? bsc * to_d(xp[r]) : 0.0;
@@ -310,8 +311,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
     if (st->status != 0) return;
-    spmv_items<VT, VT, AT>(st, rp, col, val, x, st->n_items, items, lrow, lfirst, lnch, ltk, lpart, blockIdx.x,
-                           gridDim.x, [&](int64_t r, double acc, bool, int) { y[r] = (WT)acc; });
+    spmv_items<VT, VT, AT>(st, rp, col, val, x, st->n_items, items, lrow, lfirst, lnch, ltk, lpart,
+                           blockIdx.x * WAVES + (threadIdx.x >> 6), gridDim.x * WAVES,
+                           [&](int64_t r, double acc, bool, int) { y[r] = (WT)acc; });
 }
 
 // ------------------------------------------------- reorthogonalisation
@@ -325,16 +327,90 @@ __device__ __forceinline__ bool upd_dot_active(const State* st) {
     return st->reorth >= 2 || st->mode == MODE_RESTART;
 }
 
-// Per-workgroup column sums acc[0..nc) -> part[blockIdx.x*NCMAX + k].
-template <int NC>
-__device__ __forceinline__ void publish_columns(const double (&acc)[NC], int nc, double* part, double (*red)[NC]) {
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+// The dense kernels move 16-byte chunks: R consecutive rows of one basis
+// column (2 in FP64, 4 in FP32, 8 in BF16) and the matching R rows of w.
+// The columns of a step are split over CS adjacent lanes (NCL each), so a
+// lane keeps at most 16 chunks in registers; CS lanes together own a row
+// group and combine their partial updates with shuffles.
+template <int P> struct Ch;
+template <> struct Ch<0> { typedef double2 T; static constexpr int R = 2; };
+template <> struct Ch<1> { typedef float4 T; static constexpr int R = 4; };
+template <> struct Ch<2> { typedef uint4 T; static constexpr int R = 8; };
+
+template <int P, int NC> struct Split {
+    static constexpr int NCLMAX = P == 2 ? 8 : 16;     // chunks a lane keeps in registers
+    static constexpr int CS = NC <= NCLMAX ? 1 : (NC <= 2 * NCLMAX ? 2 : (NC <= 4 * NCLMAX ? 4 : 8));
+    static constexpr int NCL = NC / CS;
+};
+
+// Keeps the compiler from holding widened copies of the packed chunks
+// between the update and the dot pass (they are re-widened instead).
+__device__ __forceinline__ void opaque(double2& c) { asm volatile("" : "+v"(c.x), "+v"(c.y)); }
+__device__ __forceinline__ void opaque(float4& c) { asm volatile("" : "+v"(c.x), "+v"(c.y), "+v"(c.z), "+v"(c.w)); }
+__device__ __forceinline__ void opaque(uint4& c) { asm volatile("" : "+v"(c.x), "+v"(c.y), "+v"(c.z), "+v"(c.w)); }
+
+__device__ __forceinline__ void unpack(const double2& c, double (&o)[2]) { o[0] = c.x; o[1] = c.y; }
+__device__ __forceinline__ void unpack(const float4& c, double (&o)[4]) {
+    o[0] = c.x; o[1] = c.y; o[2] = c.z; o[3] = c.w;
+}
+__device__ __forceinline__ double bf_lo(uint32_t u) { return (double)__uint_as_float(u << 16); }
+__device__ __forceinline__ double bf_hi(uint32_t u) { return (double)__uint_as_float(u & 0xffff0000u); }
+__device__ __forceinline__ void unpack(const uint4& c, double (&o)[8]) {
+    o[0] = bf_lo(c.x); o[1] = bf_hi(c.x); o[2] = bf_lo(c.y); o[3] = bf_hi(c.y);
+    o[4] = bf_lo(c.z); o[5] = bf_hi(c.z); o[6] = bf_lo(c.w); o[7] = bf_hi(c.w);
+}
+
+// R rows of the working vector w.
+__device__ __forceinline__ void w_load(const double* w, double (&o)[2]) { unpack(*(const double2*)w, o); }
+__device__ __forceinline__ void w_load(const float* w, double (&o)[4]) { unpack(*(const float4*)w, o); }
+__device__ __forceinline__ void w_load(const float* w, double (&o)[8]) {
+    const float4 a = *(const float4*)w, b = *((const float4*)w + 1);
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w; o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+}
+// Round x to the working precision in place; store when `st` is set.
+__device__ __forceinline__ void w_round_store(double* w, double (&x)[2], bool st) {
+    if (st) *(double2*)w = make_double2(x[0], x[1]);
+}
+__device__ __forceinline__ void w_round_store(float* w, double (&x)[4], bool st) {
+    const float4 a = make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    if (st) *(float4*)w = a;
+}
+__device__ __forceinline__ void w_round_store(float* w, double (&x)[8], bool st) {
+    const float4 a = make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
+    const float4 b = make_float4((float)x[4], (float)x[5], (float)x[6], (float)x[7]);
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w; x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    if (st) {
+        *(float4*)w = a;
+        *((float4*)w + 1) = b;
+    }
+}
+// Round x to the basis precision in place; store when `st` is set.
+__device__ __forceinline__ void v_round_store(double* v, double (&x)[2], bool st) { w_round_store(v, x, st); }
+__device__ __forceinline__ void v_round_store(float* v, double (&x)[4], bool st) { w_round_store(v, x, st); }
+__device__ __forceinline__ void v_round_store(uint16_t* v, double (&x)[8], bool st) {
+    uint32_t h[8];
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
-        if (k < nc) {
-            const double v = wave_sum(acc[k]);
-            if (ln == 0) red[wv][k] = v;
-        }
+    for (int i = 0; i < 8; ++i) {
+        h[i] = f32_to_bf16((float)x[i]);
+        x[i] = (double)__uint_as_float(h[i] << 16);
+    }
+    if (st) *(uint4*)v = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
+// Wave sums of acc[kk] over the lanes that own the same columns (lane % CS
+// equal); lanes 0..CS-1 write them to red[wave][column].  Then thread k < nc
+// publishes the workgroup sum of column k to part[blockIdx.x*NCMAX + k].
+template <int NC, int CS, int NCL>
+__device__ __forceinline__ void publish_split(const double (&acc)[NCL], int nc, double* part, double (*red)[NC]) {
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, cs = ln % CS;
+#pragma unroll
+    for (int kk = 0; kk < NCL; ++kk) {
+        double v = acc[kk];
+#pragma unroll
+        for (int o = CS; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+        if (ln < CS) red[wv][cs * NCL + kk] = v;
+    }
     __syncthreads();
     if ((int)threadIdx.x < nc)
         st_dev(&part[(int64_t)blockIdx.x * NCMAX + threadIdx.x],
@@ -375,6 +451,9 @@ template <int P, int NC>
 __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                     const typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                     double* part) {
+    using VT = typename Tr<P>::V;
+    using CT = typename Ch<P>::T;
+    constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
     __shared__ double red[BLOCK / 64][NC];
     __shared__ int s_last;
     const int j = st->j;
@@ -384,16 +463,36 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
         if (blockIdx.x == 0 && threadIdx.x == 0) st->status = -1;
         return;
     }
-    double acc[NC];
+    const int ln = threadIdx.x & 63, cs = ln % CS;
+    const int64_t rowgrp = (int64_t)(threadIdx.x >> 6) * GPW + ln / CS;
+    constexpr int64_t RB = (int64_t)(BLOCK / 64) * GPW * R;
+    double acc[NCL];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) acc[k] = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < ld; r += (int64_t)gridDim.x * BLOCK) {
-        const double wr = (double)w[r];
+    for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
+        const int64_t r0 = base + rowgrp * R;
+        double x[R];
+        w_load(w + r0, x);
+        CT ch[NCL];
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (k < nc) acc[k] += to_d(Vb[(int64_t)k * ld + r]) * wr;
+        for (int kk = 0; kk < NCL; ++kk) {
+            const int k = cs * NCL + kk;
+            if (k < nc) ch[kk] = *(const CT*)(Vb + (int64_t)k * ld + r0);
+        }
+#pragma unroll
+        for (int kk = 0; kk < NCL; ++kk) {
+            const int k = cs * NCL + kk;
+            if (k < nc) {
+                double v[R];
+                unpack(ch[kk], v);
+                double s = 0.0;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) s += v[rr] * x[rr];
+                acc[kk] += s;
+            }
+        }
     }
-    publish_columns<NC>(acc, nc, part, red);
+    publish_split<NC, CS, NCL>(acc, nc, part, red);
     if (last_block(&st->ticket[TK_DOT], gridDim.x, &s_last)) {
         reduce_columns<NC>(part, gridDim.x, nc, st->scale, st->c, red);
         if (!upd_dot_active(st)) {       // one pass: the store kernel uses c
@@ -403,14 +502,39 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
     }
 }
 
+// Partial update u = sum_k V[rows, k] coef[k] over this lane's columns,
+// completed over the CS lanes of the row group.
+template <int P, int NC>
+__device__ __forceinline__ void split_update(const typename Ch<P>::T (&ch)[Split<P, NC>::NCL], const double* coef,
+                                             int cs, int lo, int nc, double (&u)[Ch<P>::R]) {
+    constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) u[rr] = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < NCL; ++kk) {
+        const int k = cs * NCL + kk;
+        if (k >= lo && k < nc) {
+            double v[R];
+            unpack(ch[kk], v);
+            const double cf = coef[k];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) u[rr] += v[rr] * cf;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < CS; o <<= 1)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) u[rr] += __shfl_xor(u[rr], o, 64);
+}
+
 // w' = w - V c (stored in the working precision), then c2 = V^T w' and ||w'||^2.
 template <int P, int NC>
 __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                         typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                         double* part, double* part2) {
-    using VT = typename Tr<P>::V;
-    using WT = typename Tr<P>::W;
-    __shared__ double cs[NC];
+    using CT = typename Ch<P>::T;
+    constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
+    __shared__ double coef[NC];
     __shared__ double red[BLOCK / 64][NC];
     __shared__ double shd[BLOCK / 64];
     __shared__ int s_last;
@@ -421,29 +545,49 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typenam
         if (blockIdx.x == 0 && threadIdx.x == 0) st->status = -1;
         return;
     }
-    for (int k = threadIdx.x; k < NC; k += BLOCK) cs[k] = k < nc ? st->c[k] * st->scale[k] : 0.0;
+    for (int k = threadIdx.x; k < NC; k += BLOCK) coef[k] = k < nc ? st->c[k] * st->scale[k] : 0.0;
     __syncthreads();
-    double acc[NC];
+    const int ln = threadIdx.x & 63, cs = ln % CS;
+    const int64_t rowgrp = (int64_t)(threadIdx.x >> 6) * GPW + ln / CS;
+    constexpr int64_t RB = (int64_t)(BLOCK / 64) * GPW * R;
+    double acc[NCL];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) acc[k] = 0.0;
+    for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
     double nrm = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < ld; r += (int64_t)gridDim.x * BLOCK) {
-        VT v[NC];
+    for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
+        const int64_t r0 = base + rowgrp * R;
+        double x[R];
+        w_load(w + r0, x);
+        CT ch[NCL];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) v[k] = k < nc ? Vb[(int64_t)k * ld + r] : VT(0);
-        double x = (double)w[r];
+        for (int kk = 0; kk < NCL; ++kk) {
+            const int k = cs * NCL + kk;
+            if (k < nc) ch[kk] = *(const CT*)(Vb + (int64_t)k * ld + r0);
+        }
+        double u[R];
+        split_update<P, NC>(ch, coef, cs, 0, nc, u);
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (k < nc) x -= to_d(v[k]) * cs[k];
-        const WT xw = (WT)x;
-        w[r] = xw;
-        const double xr = (double)xw;
-        nrm += xr * xr;
+        for (int kk = 0; kk < NCL; ++kk) opaque(ch[kk]);
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (k < nc) acc[k] += to_d(v[k]) * xr;
+        for (int rr = 0; rr < R; ++rr) x[rr] -= u[rr];
+        w_round_store(w + r0, x, cs == 0);
+        if (cs == 0)
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) nrm += x[rr] * x[rr];
+#pragma unroll
+        for (int kk = 0; kk < NCL; ++kk) {
+            const int k = cs * NCL + kk;
+            if (k < nc) {
+                double v[R];
+                unpack(ch[kk], v);
+                double s = 0.0;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) s += v[rr] * x[rr];
+                acc[kk] += s;
+            }
+        }
     }
-    publish_columns<NC>(acc, nc, part, red);
+    publish_split<NC, CS, NCL>(acc, nc, part, red);
     nrm = block_sum(nrm, shd);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_UPD], gridDim.x, &s_last)) {
@@ -471,8 +615,9 @@ template <int P, int NC>
 __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr<P>::V* __restrict__ Vb,
                                                           const typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                           double* part2) {
-    using VT = typename Tr<P>::V;
-    __shared__ double cs[NC];
+    using CT = typename Ch<P>::T;
+    constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
+    __shared__ double coef[NC];
     __shared__ double shd[BLOCK / 64];
     __shared__ int s_last;
     const int j = st->j;
@@ -485,21 +630,33 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
     const bool second = st->second != 0;
     const int lo = (st->reorth == 0 && st->mode != MODE_RESTART) ? j : 0;
     for (int k = threadIdx.x; k < NC; k += BLOCK)
-        cs[k] = (second && k >= lo && k < nc) ? st->c2[k] * st->scale[k] : 0.0;
+        coef[k] = (second && k >= lo && k < nc) ? st->c2[k] * st->scale[k] : 0.0;
     __syncthreads();
-    VT* out = Vb + (int64_t)(j + 1) * ld;
+    const int ln = threadIdx.x & 63, cs = ln % CS;
+    const int64_t rowgrp = (int64_t)(threadIdx.x >> 6) * GPW + ln / CS;
+    constexpr int64_t RB = (int64_t)(BLOCK / 64) * GPW * R;
+    auto* out = Vb + (int64_t)(j + 1) * ld;
     double nrm = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < ld; r += (int64_t)gridDim.x * BLOCK) {
-        double x = (double)w[r];
+    for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
+        const int64_t r0 = base + rowgrp * R;
+        double x[R];
+        w_load(w + r0, x);
         if (second) {
+            CT ch[NCL];
 #pragma unroll
-            for (int k = 0; k < NC; ++k)
-                if (k >= lo && k < nc) x -= to_d(Vb[(int64_t)k * ld + r]) * cs[k];
+            for (int kk = 0; kk < NCL; ++kk) {
+                const int k = cs * NCL + kk;
+                if (k >= lo && k < nc) ch[kk] = *(const CT*)(Vb + (int64_t)k * ld + r0);
+            }
+            double u[R];
+            split_update<P, NC>(ch, coef, cs, lo, nc, u);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) x[rr] -= u[rr];
         }
-        const VT v = from_d<VT>(x);
-        out[r] = v;
-        const double d = to_d(v);
-        nrm += d * d;
+        v_round_store(out + r0, x, cs == 0);
+        if (cs == 0)
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) nrm += x[rr] * x[rr];
     }
     nrm = block_sum(nrm, shd);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
