@@ -31,6 +31,9 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.long_cap = nnz / NB + 1;
     const int64_t est_items = ceil_div(nnz, NB) + ceil_div(n, RMAX);
     p.g_spmv = (int32_t)std::max<int64_t>(1, std::min<int64_t>(SGRID, ceil_div(est_items, 4)));
+    p.n_tiles = ceil_div(nnz + n, TILE);
+    // Tiled SpMV grid: a multiple of 8 workgroups (one share per XCD).
+    p.g_tile = (int32_t)(ceil_div(std::min<int64_t>(SGRID, ceil_div(p.n_tiles, 4)), 8) * 8);
     const int kb2 = pow2_ge(K);
     const size_t vb = storage_bytes(prec), wb = work_bytes(prec);
     size_t o = 0;
@@ -43,7 +46,7 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_V = take((size_t)p.ld * (size_t)(m + 1) * vb);
     p.off_w = take((size_t)p.ld * wb);
     p.off_part = take((size_t)std::max(p.g_orth, 256) * 256 * 8);
-    p.off_part2 = take((size_t)std::max(p.g_spmv, p.g_orth) * 64 * 8);
+    p.off_part2 = take((size_t)std::max(std::max(p.g_spmv, p.g_tile), p.g_orth) * 64 * 8);
     p.off_items = take((size_t)p.items_cap * 8);
     p.off_lrow = take((size_t)p.long_cap * 4);
     p.off_lfirst = take((size_t)p.long_cap * 4);
@@ -55,6 +58,10 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_bsum = take((size_t)(ceil_div(n, 2048) + 1) * 8);
     p.off_Y = take((size_t)n * (size_t)K * 8);
     p.off_gram = take((size_t)(GRAM_PARTS + 1) * 64 * 64 * 8);
+    p.off_ob = take((size_t)(p.n_tiles + 1) * 4);
+    p.off_tk = take((size_t)p.n_tiles * 4);
+    p.off_head = take((size_t)p.n_tiles * 8);
+    p.off_tail = take((size_t)p.n_tiles * 8);
     p.bytes = o;
     return p;
 }
@@ -78,6 +85,10 @@ Bufs resolve(const Plan& p, void* base) {
     b.bsum = (uint64_t*)(c + p.off_bsum);
     b.Y = (double*)(c + p.off_Y);
     b.gram = (double*)(c + p.off_gram);
+    b.ob = (int32_t*)(c + p.off_ob);
+    b.tk = (uint32_t*)(c + p.off_tk);
+    b.head = (double*)(c + p.off_head);
+    b.tail = (double*)(c + p.off_tail);
     return b;
 }
 

@@ -16,6 +16,7 @@ constexpr int BLOCK = 256;     // threads per workgroup (4 wave64)
 constexpr int NB = 256;        // target non-zeros per row-block work item (one wavefront)
 constexpr int CH = 2048;       // non-zeros per chunk of a long row
 constexpr int RMAX = 64;       // rows per row-block work item at most
+constexpr int TILE = 1024;     // non-zeros per SpMV tile (one wavefront, 16 per lane)
 constexpr int LDPAD = 2048;    // basis leading dimension is a multiple of this
 constexpr int OGRID = 1024;    // orthogonalisation grid cap (workgroups)
 constexpr int SGRID = 2048;    // SpMV grid cap (workgroups)
@@ -59,11 +60,12 @@ struct State {
 struct Plan {
     int64_t n = 0, nnz = 0, ld = 0;
     int32_t K = 0, m = 0, prec = 0, KB = 0;
-    int32_t g_spmv = 0, g_orth = 0;
-    int64_t items_cap = 0, long_cap = 0;
+    int32_t g_spmv = 0, g_orth = 0, g_tile = 0;
+    int64_t items_cap = 0, long_cap = 0, n_tiles = 0;
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_items = 0,
            off_lrow = 0, off_lfirst = 0, off_lnch = 0, off_ltk = 0, off_lpart = 0, off_lval = 0,
-           off_scan = 0, off_bsum = 0, off_Y = 0, off_gram = 0;
+           off_scan = 0, off_bsum = 0, off_Y = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0,
+           off_tail = 0;
     size_t bytes = 0;
 };
 
@@ -93,6 +95,10 @@ struct Bufs {
     uint64_t* bsum;
     double* Y;         // Ritz vectors, column-major n x K, before normalisation
     double* gram;      // Gram partials (GRAM_PARTS x 64 x 64), then the reduced 64 x 64
+    int32_t* ob;       // SpMV tiles: first owned row of every tile (n_tiles + 1)
+    uint32_t* tk;      // split-row tickets, one per owner tile
+    double* head;      // split-row pieces at the start of a tile
+    double* tail;      // split-row pieces at the end of a tile
 };
 Bufs resolve(const Plan& p, void* base);
 

@@ -199,6 +199,22 @@ __global__ __launch_bounds__(BLOCK) void k_setup_ends(const State* st, int64_t n
     }
 }
 
+// Tile table: ob[t] = first row owned by tile t, ob[n_tiles] = n; clears the
+// split-row tickets.  Owners are non-decreasing in r, so row r writes the
+// entries of the tiles between its predecessor's owner and its own.
+__global__ __launch_bounds__(BLOCK) void k_setup_tiles(const int64_t* rp, int64_t n, int64_t n_tiles, int32_t* ob,
+                                                       uint32_t* tk) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    for (int64_t t = t0; t < n_tiles; t += stride) tk[t] = 0u;
+    if (t0 == 0) ob[n_tiles] = (int32_t)n;
+    for (int64_t r = t0; r < n; r += stride) {
+        const int64_t own = row_owner(rp, r, n_tiles);
+        const int64_t prev = r > 0 ? row_owner(rp, r - 1, n_tiles) : -1;
+        for (int64_t t = prev + 1; t <= own; ++t) ob[t] = (int32_t)r;
+    }
+}
+
 // ------------------------------------------------------------ start vector
 // V[:,0] = u rounded to the basis precision, u_r = U01(SplitMix64(seed, r));
 // scale[0] = 1/||stored u||.  Also clears w (its padding rows must stay zero).
@@ -245,10 +261,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const int64_t* _
                                                      const int32_t* __restrict__ col,
                                                      const typename Tr<P>::V* __restrict__ val,
                                                      const typename Tr<P>::V* __restrict__ Vb,
-                                                     typename Tr<P>::W* __restrict__ w, int64_t n, int64_t ld,
-                                                     const int2* __restrict__ items, const int32_t* lrow,
-                                                     const int32_t* lfirst, const int32_t* lnch, uint32_t* ltk,
-                                                     double* lpart, double* lval, double* part) {
+                                                     typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
+                                                     int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
+                                                     uint32_t* tk, double* head, double* tail, double* part) {
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
@@ -270,25 +285,22 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const int64_t* _
     const double sj = st->scale[j];
     const double bsc = j > 0 ? st->beta[j] * st->scale[j - 1] : 0.0;
     double apart = 0.0;
-    spmv_items<VT, VT, AT>(st, rp, col, val, x, st->n_items, items, lrow, lfirst, lnch, ltk, lpart,
-                           blockIdx.x * WAVES + (threadIdx.x >> 6), gridDim.x * WAVES,
-                           [&](int64_t r, double acc, bool is_long, int lid) {
-                               const double y = sj * acc;
-                               const double a = sj * to_d(x[r]) * y;
-                               const double wp = xp ? bsc * to_d(xp[r]) : 0.0;
-                               w[r] = (WT)(y - wp);
-                               if (is_long)
-                                   st_dev(&lval[lid], a);
-                               else
-                                   apart += a;
-                           });
+    // alpha = sum_r (sj x_r)(sj acc_r) is linear in every row sum, so a split
+    // row adds one term per piece and the w update waits for the whole sum.
+    spmv_tiles<VT, VT, AT>(
+        rp, col, val, x, n, nnz, n_tiles, ob, tk, head, tail,
+        [&](int64_t r, double acc) {
+            const double y = sj * acc;
+            apart += sj * to_d(x[r]) * y;
+            w[r] = (WT)(y - (xp ? bsc * to_d(xp[r]) : 0.0));
+        },
+        [&](int64_t r, double acc) { apart += sj * to_d(x[r]) * (sj * acc); },
+        [&](int64_t r, double acc) { w[r] = (WT)(sj * acc - (xp ? bsc * to_d(xp[r]) : 0.0)); });
     apart = block_sum(apart, shd);
     if (threadIdx.x == 0) st_dev(&part[blockIdx.x], apart);
     if (last_block(&st->ticket[TK_SPMV], gridDim.x, &s_last)) {
-        const double a = ordered_sum_dev(part, gridDim.x, shd);
-        const double al = ordered_sum_dev(lval, st->n_long, shd);
+        const double alpha = ordered_sum_dev(part, gridDim.x, shd);
         if (threadIdx.x == 0) {
-            const double alpha = a + al;
             st->alpha[j] = alpha;
             if (st->reorth == 0) {          // three-term recurrence only
                 st->c2[j] = alpha;
@@ -298,22 +310,22 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const int64_t* _
     }
 }
 
-// Plain y = A x (component entry point), same partition and kernel core.
+// Plain y = A x (component entry point), same tiles and kernel core.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col,
                                                       const typename Tr<P>::V* __restrict__ val,
                                                       const typename Tr<P>::V* __restrict__ x,
-                                                      typename Tr<P>::W* __restrict__ y, const int2* __restrict__ items,
-                                                      const int32_t* lrow, const int32_t* lfirst, const int32_t* lnch,
-                                                      uint32_t* ltk, double* lpart) {
+                                                      typename Tr<P>::W* __restrict__ y, int64_t n, int64_t nnz,
+                                                      int64_t n_tiles, const int32_t* __restrict__ ob, uint32_t* tk,
+                                                      double* head, double* tail) {
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
     if (st->status != 0) return;
-    spmv_items<VT, VT, AT>(st, rp, col, val, x, st->n_items, items, lrow, lfirst, lnch, ltk, lpart,
-                           blockIdx.x * WAVES + (threadIdx.x >> 6), gridDim.x * WAVES,
-                           [&](int64_t r, double acc, bool, int) { y[r] = (WT)acc; });
+    spmv_tiles<VT, VT, AT>(
+        rp, col, val, x, n, nnz, n_tiles, ob, tk, head, tail, [&](int64_t r, double acc) { y[r] = (WT)acc; },
+        [&](int64_t, double) {}, [&](int64_t r, double acc) { y[r] = (WT)acc; });
 }
 
 // ------------------------------------------------- reorthogonalisation
@@ -708,8 +720,8 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
     VT* V = (VT*)b.V;
     WT* w = (WT*)b.w;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL((k_spmv_step<P>), dim3(p.g_spmv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, (const VT*)a.val,
-                       V, w, a.n, p.ld, b.items, b.lrow, b.lfirst, b.lnch, b.ltk, b.lpart, b.lval, b.part2);
+    hipLaunchKernelGGL((k_spmv_step<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, (const VT*)a.val,
+                       V, w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
     if (ev) (void)hipEventRecord(ev[1], s);
     const int nb = nc_bucket(ncols);
 #define LZ_ORTH_CASE(NCV)                                                                                  \
@@ -763,6 +775,7 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
                        p.long_cap, p.K, b.items, b.lrow, b.lfirst, b.lnch, b.ltk, b.st);
     const int gi = (int)std::min<int64_t>((p.items_cap + BLOCK - 1) / BLOCK, 4096);
     hipLaunchKernelGGL(k_setup_ends, dim3(gi), dim3(BLOCK), 0, s, b.st, n, b.items, b.lrow);
+    hipLaunchKernelGGL(k_setup_tiles, dim3(g), dim3(BLOCK), 0, s, a.rowptr, n, p.n_tiles, b.ob, b.tk);
     return hipGetLastError();
 }
 
@@ -786,25 +799,20 @@ hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int P>
+static void spmv_plain_p(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y, hipStream_t s) {
+    using VT = typename Tr<P>::V;
+    using WT = typename Tr<P>::W;
+    hipLaunchKernelGGL((k_spmv_plain<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                       (const VT*)a.val, (const VT*)x, (WT*)y, a.n, a.nnz, p.n_tiles, b.ob, b.tk, b.head, b.tail);
+}
+
 hipError_t launch_spmv_plain(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y, hipStream_t s) {
     switch (p.prec) {
-        case 0:
-            hipLaunchKernelGGL(k_spmv_plain<0>, dim3(p.g_spmv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
-                               (const double*)a.val, (const double*)x, (double*)y, b.items, b.lrow, b.lfirst,
-                               b.lnch, b.ltk, b.lpart);
-            break;
-        case 1:
-            hipLaunchKernelGGL(k_spmv_plain<1>, dim3(p.g_spmv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
-                               (const float*)a.val, (const float*)x, (float*)y, b.items, b.lrow, b.lfirst, b.lnch,
-                               b.ltk, b.lpart);
-            break;
-        case 2:
-            hipLaunchKernelGGL(k_spmv_plain<2>, dim3(p.g_spmv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
-                               (const uint16_t*)a.val, (const uint16_t*)x, (float*)y, b.items, b.lrow, b.lfirst,
-                               b.lnch, b.ltk, b.lpart);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 0: spmv_plain_p<0>(p, b, a, x, y, s); break;
+        case 1: spmv_plain_p<1>(p, b, a, x, y, s); break;
+        case 2: spmv_plain_p<2>(p, b, a, x, y, s); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -1,21 +1,32 @@
-// CSR SpMV core over the row-partition work items (Algorithm 1, the SpMV
-// line), shared by the Lanczos step, the standalone SpMV and the residual
-// check.
+// CSR SpMV core over merge-path tiles (Algorithm 1, the SpMV line), shared by
+// the Lanczos step and the standalone SpMV.
 //
-// Work items are built once per matrix and are sized for one wavefront: a
-// row block is a run of consecutive short rows with at most 2*NB non-zeros
-// and RMAX = 64 rows; a long row (more than NB non-zeros) is cut into chunks
-// of CH non-zeros.
-//   Row block: every lane loads its col/val pairs first and then gathers x,
-//     so all of a wavefront's loads are in flight together; the products are
-//     staged in the wavefront's LDS slice and each row is summed by a
-//     power-of-two group of lanes.
-//   Long-row chunk: the wavefront sums CH products; chunk sums are published
-//     device-coherently and the last chunk of the row to finish adds them in
-//     chunk order.
-// epi(r, acc, is_long, lid) receives every row sum exactly once: for a row
-// block from its group leader lane, for a long row from lane 0 of the
-// finalising wavefront.
+// Walk the matrix as one sequence of items: the entries of row 0, an end
+// marker for row 0, the entries of row 1, its end marker, and so on
+// (nnz + n items; entry p of row r is item p + r, the end of row r is item
+// rowptr[r+1] + r).  Tile t is items [t*TILE, (t+1)*TILE), one tile per
+// wavefront at a time, so a tile holds at most TILE entries plus row ends
+// whatever the row lengths (long rows, empty rows).  Row r is owned by the
+// tile holding its end marker; tile t owns rows ob[t] .. ob[t+1]-1 and its
+// entries are [t*TILE - ob[t], (t+1)*TILE - ob[t+1]).  A tile
+//   * loads its col/val entries, gathers x and keeps the products in its
+//     LDS slice;
+//   * sums its owned rows: rows of up to LONGR entries by one lane each,
+//     longer ones by the whole wavefront;
+//   * may hold a head piece (its first owned row began in an earlier tile)
+//     and a tail piece (row ob[t+1] continues into later tiles).
+// A row whose first entry lies in tile t1 and whose end lies in tile t2 > t1
+// has tail pieces in t1..t2-1 and the head piece in t2.  Every piece is
+// published device-coherently and counted on the owner's ticket; the last
+// piece to arrive adds all of them in tile order, so the row sum does not
+// depend on which wavefront finishes last.
+//
+// The epilogue is three callbacks, all called by one lane with a value that
+// is final for that lane:
+//   row(r, s)    owned row r with its whole sum s;
+//   piece(r, s)  one piece of a split row (for sums that are linear in the
+//                row sum, such as alpha);
+//   fin(r, s)    a split row's whole sum, from the finalising wavefront.
 #pragma once
 
 #include "lz_device.h"
@@ -23,7 +34,8 @@
 namespace lz {
 
 constexpr int WAVES = BLOCK / 64;
-constexpr int PPT = 2 * NB / 64;      // row-block products per lane
+constexpr int TP = TILE / 64;          // tile entries per lane
+constexpr int LONGR = 64;              // rows longer than this are summed by the whole wavefront
 
 // Orders this wavefront's LDS writes before its later LDS reads (LDS
 // operations of one wavefront complete in order; this stops the compiler
@@ -48,92 +60,164 @@ __device__ __forceinline__ bool last_wave(uint32_t* ticket, uint32_t count) {
     return last;
 }
 
-// Each wavefront walks work items wid, wid + nwaves, ... independently (no
-// workgroup barrier per item, so many items are in flight per CU).
-template <class VT, class XT, class AT, class Epi>
-__device__ __forceinline__ void spmv_items(State* st, const int64_t* __restrict__ rp,
-                                           const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                           const XT* __restrict__ x, int nitems, const int2* __restrict__ items,
-                                           const int32_t* __restrict__ lrow, const int32_t* __restrict__ lfirst,
-                                           const int32_t* __restrict__ lnch, uint32_t* ltk, double* lpart,
-                                           int wid, int nwaves, Epi&& epi) {
-    __shared__ AT prod[WAVES][2 * NB];
+// Tile of item i, clamped so that malformed input cannot index outside the
+// tile tables.
+__device__ __forceinline__ int64_t item_tile(int64_t i, int64_t n_tiles) {
+    const int64_t t = i / TILE;
+    return t < 0 ? 0 : (t >= n_tiles ? n_tiles - 1 : t);
+}
+// Owner tile of row r (the tile of its end marker).
+__device__ __forceinline__ int64_t row_owner(const int64_t* rp, int64_t r, int64_t n_tiles) {
+    return item_tile(rp[r + 1] + r, n_tiles);
+}
+
+// Sum of p[b..e) in four interleaved chains, combined in a fixed order.
+template <class AT>
+__device__ __forceinline__ AT lds_sum(const AT* p, int b, int e) {
+    AT s0 = AT(0), s1 = AT(0), s2 = AT(0), s3 = AT(0);
+    int k = b;
+    for (; k + 4 <= e; k += 4) {
+        s0 += p[k];
+        s1 += p[k + 1];
+        s2 += p[k + 2];
+        s3 += p[k + 3];
+    }
+    for (; k < e; ++k) s0 += p[k];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Whole-wavefront sum of p[b..e): lane-strided partials, then the butterfly.
+template <class AT>
+__device__ __forceinline__ AT lds_wave_sum(const AT* p, int b, int e, int lane) {
+    AT s = AT(0);
+    for (int k = b + lane; k < e; k += 64) s += p[k];
+    return wave_sum(s);
+}
+
+// Tiles handled by this wavefront: the tile range is split evenly over the
+// eight XCDs (workgroup i runs on XCD i mod 8), so neighbouring tiles, which
+// gather neighbouring parts of x in a banded matrix, share one L2.
+struct TileRange {
+    int64_t first, end, stride;
+};
+__device__ __forceinline__ TileRange wave_tiles(int64_t n_tiles) {
+    const int64_t xcd = blockIdx.x & 7, nb8 = gridDim.x >> 3;
+    const int64_t lo = n_tiles * xcd / 8, hi = n_tiles * (xcd + 1) / 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)(blockIdx.x >> 3) * WAVES + wave;
+    return {lo + w, hi, nb8 * WAVES};
+}
+
+// Adds the pieces of the split row r (tail pieces in tiles t1..t2-1, head
+// piece in t2) in tile order; called by every lane of the finalising
+// wavefront, returns the sum in all lanes.
+__device__ __forceinline__ double split_total(const double* head, const double* tail, int64_t t1, int64_t t2,
+                                              int lane) {
+    double s = 0.0;
+    for (int64_t i = t1 + lane; i < t2; i += 64) s += ld_dev(&tail[i]);
+    s = wave_sum(s);
+    return s + ld_dev(&head[t2]);
+}
+
+template <class VT, class XT, class AT, class Row, class Piece, class Fin>
+__device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, const XT* __restrict__ x, int64_t n,
+                                           int64_t nnz, int64_t n_tiles, const int32_t* __restrict__ ob,
+                                           uint32_t* tk, double* head, double* tail, Row&& row, Piece&& piece,
+                                           Fin&& fin) {
+    __shared__ AT prod[WAVES][TILE];
     const int lane = threadIdx.x & 63;
     AT* pw = prod[threadIdx.x >> 6];
-    for (int it = wid; it < nitems; it += nwaves) {
-        const int2 item = items[it];
-        if (item.x >= 0) {
-            const int64_t rs = item.x, re = item.y;
-            const int64_t ps = rp[rs];
-            const int64_t cnt64 = rp[re] - ps;
-            const int nr = (int)(re - rs);
-            if (cnt64 < 0 || cnt64 > 2 * NB || nr > 64) {   // cannot happen for a validated partition
-                if (lane == 0) st->status = -4;
-                continue;
-            }
-            const int cnt = (int)cnt64;
-            int tpr = 1;
-            while (tpr < 64 && tpr * 2 * nr <= 64) tpr <<= 1;
-            const int row = lane / tpr, sub = lane & (tpr - 1);
-            int b0 = 0, e0 = 0;
-            if (row < nr) {
-                b0 = (int)(rp[rs + row] - ps);
-                e0 = (int)(rp[rs + row + 1] - ps);
-            }
-            int ci[PPT];
-            VT vv[PPT];
+    const TileRange tr = wave_tiles(n_tiles);
+    const int64_t items = nnz + n;
+    int64_t r_lo = 0, r_hi = 0;
+    if (tr.first < tr.end) {
+        r_lo = ob[tr.first];
+        r_hi = ob[tr.first + 1];
+    }
+    for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
+        const int64_t t0 = t * TILE - r_lo;
+        const int cnt = (int)(min<int64_t>((t + 1) * TILE, items) - r_hi - t0);
+        // Row bounds of the next tile, loaded while this one works.
+        const int64_t tn = t + tr.stride;
+        int64_t n_lo = 0, n_hi = 0;
+        if (tn < tr.end) {
+            n_lo = ob[tn];
+            n_hi = ob[tn + 1];
+        }
+        // Entries of the tile, then the gathers of x.  Lanes past the end
+        // re-read the tile's last entry (same cache line), so every load is
+        // unconditional; their products land beyond cnt and are never read.
+        if (cnt > 0) {
+            int ci[TP];
+            VT vv[TP];
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                const int t = lane + q * 64;
-                if (t < cnt) {
-                    ci[q] = col[ps + t];
-                    vv[q] = val[ps + t];
+            for (int q = 0; q < TP; ++q) {
+                const int64_t p = t0 + min(q * 64 + lane, cnt - 1);
+                ci[q] = col[p];
+                vv[q] = val[p];
+            }
+#pragma unroll
+            for (int q = 0; q < TP; ++q) pw[q * 64 + lane] = to_a(vv[q], AT(0)) * to_a(x[ci[q]], AT(0));
+        }
+        wave_sync();
+        // Owned rows, 64 at a time.
+        const bool split_head = r_lo < r_hi && rp[r_lo] < t0;
+        double head_s = 0.0;
+        for (int64_t base = r_lo; base < r_hi; base += 64) {
+            const int64_t r = base + lane;
+            const bool valid = r < r_hi;
+            int b = 0, e = 0;
+            if (valid) {
+                b = (int)(max(rp[r], t0) - t0);
+                e = (int)(rp[r + 1] - t0);
+            }
+            const bool islong = valid && e - b > LONGR;
+            AT s = (valid && !islong) ? lds_sum(pw, b, e) : AT(0);
+            uint64_t mask = __ballot(islong);
+            while (mask) {
+                const int L = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const AT ss = lds_wave_sum(pw, __shfl(b, L, 64), __shfl(e, L, 64), lane);
+                if (lane == L) s = ss;
+            }
+            if (valid) {
+                if (split_head && r == r_lo) {
+                    head_s = (double)s;
+                    piece(r, head_s);
+                } else {
+                    row(r, (double)s);
                 }
-            }
-#pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                const int t = lane + q * 64;
-                if (t < cnt) pw[t] = to_a(vv[q], AT(0)) * to_a(x[ci[q]], AT(0));
-            }
-            wave_sync();
-            AT s = AT(0);
-            for (int k = b0 + sub; k < e0; k += tpr) s += pw[k];
-            for (int o = tpr >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-            if (row < nr && sub == 0) epi(rs + row, (double)s, false, 0);
-            wave_sync();
-        } else {
-            const int lid = -1 - item.x;
-            const int64_t r = lrow[lid];
-            const int64_t p0 = rp[r] + (int64_t)item.y * CH;
-            const int64_t p1 = min(p0 + (int64_t)CH, rp[r + 1]);
-            const int cnt = (int)(p1 - p0);
-            AT s = AT(0);
-            for (int base = 0; base < cnt; base += PPT * 64) {
-                int ci[PPT];
-                VT vv[PPT];
-#pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    const int t = base + lane + q * 64;
-                    if (t < cnt) {
-                        ci[q] = col[p0 + t];
-                        vv[q] = val[p0 + t];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    const int t = base + lane + q * 64;
-                    if (t < cnt) s += to_a(vv[q], AT(0)) * to_a(x[ci[q]], AT(0));
-                }
-            }
-            s = wave_sum(s);
-            if (lane == 0) st_dev(&lpart[it], (double)s);
-            if (last_wave(&ltk[lid], (uint32_t)lnch[lid]) && lane == 0) {
-                const int f = lfirst[lid], nc = lnch[lid];
-                double tot = 0.0;
-                for (int q = 0; q < nc; ++q) tot += ld_dev(&lpart[f + q]);
-                epi(r, tot, true, lid);
             }
         }
+        // Head piece: publish, count, finish the row if it is the last piece.
+        if (split_head) {
+            if (lane == 0) st_dev(&head[t], head_s);
+            const int64_t t1 = item_tile(rp[r_lo] + r_lo, n_tiles);
+            if (last_wave(&tk[t], (uint32_t)(t - t1 + 1))) {
+                const double tot = split_total(head, tail, t1, t, lane);
+                if (lane == 0) fin(r_lo, tot);
+            }
+        }
+        // Tail piece of the row that continues past this tile.
+        if (r_hi < n) {
+            const int64_t rb = rp[r_hi];
+            if (rb < t0 + cnt) {
+                const AT ss = lds_wave_sum(pw, (int)(max(rb, t0) - t0), cnt, lane);
+                if (lane == 0) {
+                    piece(r_hi, (double)ss);
+                    st_dev(&tail[t], (double)ss);
+                }
+                const int64_t t1 = item_tile(rb + r_hi, n_tiles), t2 = row_owner(rp, r_hi, n_tiles);
+                if (last_wave(&tk[t2], (uint32_t)(t2 - t1 + 1))) {
+                    const double tot = split_total(head, tail, t1, t2, lane);
+                    if (lane == 0) fin(r_hi, tot);
+                }
+            }
+        }
+        wave_sync();
+        r_lo = n_lo;
+        r_hi = n_hi;
     }
 }
 

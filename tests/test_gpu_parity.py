@@ -45,7 +45,38 @@ def spmv_cases():
         edges.add((i, (i * 31 + 5) % n) if i != (i * 31 + 5) % n else (i, (i + 1) % n))
     edges = sorted(e for e in edges if e[0] != e[1])
     cases["mixed6000"] = synth.from_edges(n, edges, weights=rng.uniform(-1, 1, len(edges)))
+    # Hub-first relabelling: the longest rows lead and every empty row
+    # (isolated vertex) sits at the end.
+    cases["rmat14_hubfirst"] = hub_first(*synth.rmat(14, 8, seed=13))
+    # Long runs of empty rows before, between and after a few short rows.
+    cases["empty_runs"] = rows_with_lengths([0] * 3000 + [3, 1, 2] + [0] * 2500 + [5] + [0] * 4000, seed=6)
+    # Row lengths around the 1024-item tile: a row of length L and its end
+    # marker take L + 1 items.
+    cases["tile_edges"] = rows_with_lengths([1023, 1023, 1, 1022, 1024, 2047, 0, 2048, 3071, 7, 1023], seed=7)
     return cases
+
+
+def hub_first(rp, c, v):
+    """Symmetric relabelling by non-increasing row length (stable)."""
+    n = rp.size - 1
+    deg = np.diff(rp)
+    order = np.argsort(-deg, kind="stable")
+    new = np.empty(n, np.int64)
+    new[order] = np.arange(n)
+    nd = deg[order]
+    nrp = np.concatenate([[0], np.cumsum(nd)]).astype(np.int64)
+    idx = np.repeat(rp[order] - nrp[:-1], nd) + np.arange(nrp[-1])
+    return nrp, new[c[idx]].astype(np.int32), v[idx]
+
+
+def rows_with_lengths(lens, seed):
+    """Square CSR with the given row lengths, random columns and values
+    (not symmetric: the SpMV does not need it)."""
+    rng = np.random.default_rng(seed)
+    n = len(lens)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    c = rng.integers(0, n, int(rp[-1])).astype(np.int32)
+    return rp, c, rng.uniform(-1, 1, c.size)
 
 
 SPMV = spmv_cases()
@@ -105,6 +136,21 @@ def test_fp64_er10000_k8_m24_matches_oracle():
     assert np.all(cos >= 1 - 1e-9), cos
     np.testing.assert_allclose(rep["abs_resid"], ref["abs_resid"], rtol=1e-7)
     assert rep["restarts"] == 0 and rep["m_eff"] == m
+
+
+@pytest.mark.parametrize("name", ["rmat14_hubfirst", "mixed6000"])
+def test_fp64_solve_on_skewed_rows_matches_oracle(name):
+    # Hub rows spanning many SpMV tiles and runs of empty rows, through the
+    # whole solve: the Lanczos coefficients follow the oracle's.
+    rp, c, v = SPMV[name]
+    K, m = 4, 16
+    vals, Y, rep = run_gpu(rp, c, v, K, m, "fp64", seed=3)
+    ref = oracle.topk(rp, c, v, K, m, seed=3)
+    print(f"{name}: eig rel err {eig_rel_err(vals, ref['vals']):.3e} restarts {rep['restarts']}")
+    assert rep["restarts"] == ref["restarts"]
+    assert eig_rel_err(vals, ref["vals"]) <= 1e-10
+    np.testing.assert_allclose(rep["alpha"][:m], ref["alpha"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(rep["beta"][1:m], ref["beta"][1:m], rtol=1e-10, atol=1e-12)
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 37, 2047, 2049, 4097])
