@@ -11,7 +11,15 @@ FP64 runs see the same matrix; K = 16, m = 48.  The headline is the FP32
 storage mode (FP32 values/basis/SpMV accumulation, FP64 dots, reorth,
 Jacobi); the FP64 mode runs on the same input for comparison.
 
+Other workloads (--workload): er10k (Erdos-Renyi n = 10 000, K = 8, m = 24,
+FP64), rmat23 (scale 23, edge factor 16, BF16 mode against an FP64 run,
+K = 24, m = 64), rmat26 (scale 26, edge factor 16, FP32 mode against an FP64
+run, K = 8, m = 32), serving (a stream of requests through the
+continuous-batching server: saturation throughput per precision and Poisson
+arrivals at fractions of the FP64 capacity).
+
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+[--workload NAME]
 """
 from __future__ import annotations
 
@@ -49,6 +57,11 @@ def workload(name: str):
         v = synth.round_values(v, "bf16")
         return dict(rp=rp, col=c, val=v, K=24, m=64, precisions=("bf16", "fp64"),
                     desc="R-MAT scale 23, edge factor 16, U(0,1) weights rounded to BF16")
+    if name == "rmat26":
+        rp, c, v = synth.rmat(26, 16, seed=0)
+        v = synth.round_values(v, "fp32")
+        return dict(rp=rp, col=c, val=v, K=8, m=32, precisions=("fp32", "fp64"),
+                    desc="R-MAT scale 26, edge factor 16, U(0,1) weights rounded to FP32")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -57,6 +70,38 @@ def spmv_bytes(n: int, nnz: int, precision: str) -> int:
     int64 row pointer, one read of x and of v_{j-1}, one write of w."""
     vb, wb = BYTES[precision]
     return nnz * (4 + vb) + (n + 1) * 8 + n * (2 * vb + wb)
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 of the sources of the Lanczos-step SpMV kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lz_spmv.h", "lz_kernels.hip", "lz_device.h", "lz_internal.h"):
+        with open(os.path.join(ROOT, "paper_2201_07498_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration), or
+    None when no summary matches this workload or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_spmv_step-{workload}-{precision}-traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("- ") and ": " in ln:
+                k, v = ln[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run_mode(lz, dev_csr, K, m, precision, steps, warmup, ws):
@@ -170,12 +215,17 @@ def serving_main(args):
         print(f"[serving] saturation {name}: {len(reqs) / el:.1f} solves/s, p50 {np.percentile(lat, 50):.1f} ms, "
               f"p99 {np.percentile(lat, 99):.1f} ms, arena peak {st['arena_peak'] / 2**30:.1f} GiB",
               file=sys.stderr, flush=True)
+    # Poisson arrivals of the mix at fractions of the measured FP64 capacity.
     cap = len(reqs) / runs["fp64"]["elapsed"]
-    rate = 0.8 * cap
-    arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, len(reqs)))
-    el, lat, out, st = run_stream(lz, pool_dev, reqs, arr, None, budget, args.slots)
-    print(f"[serving] poisson mix at {rate:.1f} req/s: p50 {np.percentile(lat, 50):.1f} ms, "
-          f"p99 {np.percentile(lat, 99):.1f} ms", file=sys.stderr, flush=True)
+    sweep = []
+    for frac in (0.5, 0.8, 1.0, 1.5):
+        rate = frac * cap
+        arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, len(reqs)))
+        el, lat, out, st = run_stream(lz, pool_dev, reqs, arr, None, budget, args.slots)
+        sweep.append({"rate_per_s": rate, "fraction_of_fp64_capacity": frac, "solves_per_s": len(reqs) / el,
+                      "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}})
+        print(f"[serving] poisson mix at {rate:.1f} req/s ({frac}x FP64 capacity): {len(reqs) / el:.1f} solves/s, "
+              f"p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms", file=sys.stderr, flush=True)
     err = []
     for (v32, _), (v64, _) in zip(runs["fp32"]["out"], runs["fp64"]["out"]):
         den = np.maximum(np.abs(v64), 1e-12 * np.max(np.abs(v64)))
@@ -201,8 +251,7 @@ def serving_main(args):
                    "degree U[4,32], K in {4,8,16}, m=3K", "requests": len(reqs), "pool": len(pool),
                    "slots": args.slots, "budget_gb": args.budget_gb, "parallelism": "single-gpu"},
         "fp32": f(runs["fp32"]), "fp64": f(runs["fp64"]), "mix": f(runs["mix"]),
-        "poisson_mix": {"rate_per_s": rate, "latency_ms": {"p50": float(np.percentile(lat, 50)),
-                                                            "p99": float(np.percentile(lat, 99))}},
+        "poisson_mix": sweep,
         "speedup_fp32_vs_fp64": runs["fp64"]["elapsed"] / runs["fp32"]["elapsed"],
         "eig_rel_err_fp32_vs_fp64": {"max": float(err.max()), "median": float(np.median(err))},
         "arena_peak_gib": runs["mix"]["stats"]["arena_peak"] / 2 ** 30,
@@ -217,10 +266,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
-    ap.add_argument("--pool", type=int, default=16, help="serving: distinct matrices")
+    ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
+    ap.add_argument("--pool", type=int, default=32, help="serving: distinct matrices")
     ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM arena")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain copy kernel (1 GiB read + 1 GiB written, three launches) whose "
+                         "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic of the other kernels")
+    ap.add_argument("--precisions", default=None, help="comma list overriding the workload's precisions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -234,8 +287,17 @@ def main():
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from gpu_util import device_csr, eig_rel_err
 
+    if args.calibrate_copy:
+        src = torch.rand(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     t = time.perf_counter()
     W = workload(args.workload)
+    if args.precisions:
+        W["precisions"] = tuple(args.precisions.split(","))
     rp, col, val, K, m = W["rp"], W["col"], W["val"], W["K"], W["m"]
     n, nnz = rp.size - 1, int(rp[-1])
     print(f"[bench] workload {args.workload}: n={n} nnz={nnz} K={K} m={m} (gen {time.perf_counter() - t:.1f}s)",
@@ -303,16 +365,31 @@ def main():
                                  "orth_per_step": r["t_orth_ms"], "finish": r["t_finish_ms"]}}
         line[f"speedup_{head}_vs_{p}"] = line["value"] / line[p]["solves_per_s"]
 
+    line["roofline"]["traffic"] = measured_traffic(args.workload, head)
+    if "fp64" in results and head != "fp64":
+        # The FP64 run is the reference of the reduced-precision mode.
+        line[f"eig_rel_err_{head}_vs_fp64_gpu"] = eig_rel_err(R["vals"], results["fp64"]["vals"])
     if not args.no_cpu:
         import oracle
-        t = time.perf_counter()
-        ref = oracle.topk(rp, col, val, K, m, seed=0, report=False)
-        dt = time.perf_counter() - t
-        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                                "sample": f"one whole FP64 oracle solve of the same workload ({dt:.1f} s)"}
-        for p, r in results.items():
-            key = "eig_rel_err" if p == head else f"eig_rel_err_{p}"
-            line[key] = eig_rel_err(r["vals"], ref["vals"])
+        if nnz <= 64_000_000:
+            t = time.perf_counter()
+            ref = oracle.topk(rp, col, val, K, m, seed=0, report=False)
+            dt = time.perf_counter() - t
+            line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                    "sample": f"one whole FP64 oracle solve of the same workload ({dt:.1f} s)"}
+            for p, r in results.items():
+                key = "eig_rel_err" if p == head else f"eig_rel_err_{p}"
+                line[key] = eig_rel_err(r["vals"], ref["vals"])
+        else:
+            # Bounded sample: two oracle Lanczos steps on the whole matrix; a
+            # solve is m such steps (its Jacobi and Ritz parts are not timed).
+            steps = 2
+            t = time.perf_counter()
+            oracle.lanczos(rp, col, val, steps, seed=0)
+            dt = (time.perf_counter() - t) / steps * m
+            line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                    "sample": f"{steps} FP64 oracle Lanczos steps on the whole matrix, "
+                                              f"scaled to m={m} steps ({dt:.0f} s per solve)"}
     print(json.dumps(line), flush=True)
 
 

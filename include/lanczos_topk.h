@@ -66,6 +66,19 @@ typedef enum {
 #define LZ_REORTH_SELECTIVE 3  /* second pass only when its correction
                                   exceeds the storage rounding of w */
 
+/* Row order of the solve.  Algorithm 1 applied to P A P^T (P a permutation)
+   has the same Ritz values, and its Ritz vectors are P y; the library may
+   relabel the rows and columns of the matrix hub-first (a stable sort by
+   degree class, longest rows first) so that the gathers of the SpMV hit a
+   compact, cached part of the vector.  Start and restart vectors are drawn
+   by original row index and the Ritz vectors come back in original order,
+   so only rounding differs.  The relabelled copy lives in the workspace. */
+#define LZ_REORDER_OFF 0       /* solve in the caller's order */
+#define LZ_REORDER_HUBS 1      /* always relabel hub-first */
+#define LZ_REORDER_AUTO 2      /* relabel when n >= 2^17 and the longest row
+                                  holds at least 32 times the mean row
+                                  length (power-law graphs); default */
+
 typedef struct lz_options {
     uint64_t seed;           /* start vector: u_r = U01(SplitMix64(seed, r)),
                                 v_1 = u/||u||; default 0 */
@@ -76,7 +89,7 @@ typedef struct lz_options {
     size_t workspace_bytes;
     int32_t profile;         /* 1: time the phases with HIP events recorded
                                 on `stream` (fills the t_* report fields) */
-    int32_t reserved;
+    int32_t reorder;         /* LZ_REORDER_*; default LZ_REORDER_AUTO */
 } lz_options;
 
 /* Results of one solve, filled on the host when the call returns. */
@@ -98,11 +111,13 @@ typedef struct lz_report {
                                         v_{i+1} (1-based), beta[m] = beta_last */
     double theta[LZ_MAX_STEPS];      /* all m Ritz values (Jacobi order) */
     /* Phase timings in milliseconds (only with lz_options.profile = 1). */
-    double t_setup_ms;       /* input checks, row partition, start vector */
+    double t_setup_ms;       /* input checks, relabelling, tiles, start vector */
     double t_lanczos_ms;     /* all Lanczos iterations */
     double t_spmv_ms;        /* mean duration of one SpMV launch */
     double t_orth_ms;        /* mean duration of one step's reorthogonalisation */
     double t_finish_ms;      /* Jacobi, selection, Ritz vectors, report */
+    int32_t reordered;       /* 1: the solve ran on the hub-first relabelling */
+    int32_t pad;
 } lz_report;
 
 /* Fills *opt with the defaults above. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblanczos_topk.so")
 LZ_FP64, LZ_FP32, LZ_BF16 = 0, 1, 2
 PRECISION = {"fp64": LZ_FP64, "fp32": LZ_FP32, "bf16": LZ_BF16}
 REORTH = {"none": 0, "once": 1, "twice": 2, "selective": 3}
+REORDER = {"off": 0, "hubs": 1, "auto": 2}
 MAX_STEPS = 64
 STATUS = {0: "LZ_OK", -1: "LZ_ERR_INVALID_ARG", -2: "LZ_ERR_OUT_OF_MEMORY", -3: "LZ_ERR_HIP",
           -4: "LZ_ERR_WORKSPACE_TOO_SMALL", -5: "LZ_ERR_TOO_LARGE", -6: "LZ_ERR_NOT_CONVERGED",
@@ -33,7 +34,7 @@ class LanczosError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("reorth", ctypes.c_int32), ("report", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("reorder", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -45,7 +46,7 @@ class Report(ctypes.Structure):
                 ("beta", ctypes.c_double * (MAX_STEPS + 1)), ("theta", ctypes.c_double * MAX_STEPS),
                 ("t_setup_ms", ctypes.c_double), ("t_lanczos_ms", ctypes.c_double),
                 ("t_spmv_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double),
-                ("t_finish_ms", ctypes.c_double)]
+                ("t_finish_ms", ctypes.c_double), ("reordered", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def to_dict(self, K: int, m: int) -> dict:
         return dict(status=self.status, m_eff=self.m_eff, restarts=self.restarts,
@@ -55,7 +56,8 @@ class Report(ctypes.Structure):
                     mean_angle_deg=self.mean_angle_deg, alpha=np.array(self.alpha[:m]),
                     beta=np.array(self.beta[:m + 1]), theta=np.array(self.theta[:m]),
                     t_setup_ms=self.t_setup_ms, t_lanczos_ms=self.t_lanczos_ms,
-                    t_spmv_ms=self.t_spmv_ms, t_orth_ms=self.t_orth_ms, t_finish_ms=self.t_finish_ms)
+                    t_spmv_ms=self.t_spmv_ms, t_orth_ms=self.t_orth_ms, t_finish_ms=self.t_finish_ms,
+                    reordered=bool(self.reordered))
 
 
 _lib = None
@@ -118,7 +120,7 @@ def workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
 
 def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
          report: bool = True, stream=None, workspace=None, nnz: int | None = None,
-         profile: bool = False, out=None):
+         profile: bool = False, out=None, reorder="auto"):
     """Top-K eigenpairs.  Returns (vals[K], vecs[n, K] view of the column-major
     output, report dict)."""
     import torch
@@ -139,6 +141,7 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
     opt.reorth = REORTH[reorth] if isinstance(reorth, str) else int(reorth)
     opt.report = 1 if report else 0
     opt.profile = 1 if profile else 0
+    opt.reorder = REORDER[reorder] if isinstance(reorder, str) else int(reorder)
     if workspace is not None:
         opt.workspace = ctypes.c_void_p(workspace.data_ptr())
         opt.workspace_bytes = workspace.numel() * workspace.element_size()

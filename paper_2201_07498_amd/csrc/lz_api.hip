@@ -27,15 +27,13 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.ld = ceil_div(n, LDPAD) * LDPAD;
     p.KB = (int32_t)std::max<int64_t>(8, ceil_div(K, 8) * 8);
     p.g_orth = (int32_t)std::min<int64_t>(OGRID, p.ld / BLOCK);
-    p.items_cap = ceil_div(n, RMAX) + 3 * ceil_div(nnz, NB) + ceil_div(nnz, CH) + 2;
-    p.long_cap = nnz / NB + 1;
-    const int64_t est_items = ceil_div(nnz, NB) + ceil_div(n, RMAX);
-    p.g_spmv = (int32_t)std::max<int64_t>(1, std::min<int64_t>(SGRID, ceil_div(est_items, 4)));
     p.n_tiles = ceil_div(nnz + n, TILE);
     // Tiled SpMV grid: a multiple of 8 workgroups (one share per XCD).
     p.g_tile = (int32_t)(ceil_div(std::min<int64_t>(SGRID, ceil_div(p.n_tiles, 4)), 8) * 8);
     const int kb2 = pow2_ge(K);
     const size_t vb = storage_bytes(prec), wb = work_bytes(prec);
+    // Scan scratch: the degree-class histogram (64 classes per 4096-row chunk).
+    const int64_t scan_n = std::max<int64_t>(n, 64 * ceil_div(n, 4096));
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -46,22 +44,21 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_V = take((size_t)p.ld * (size_t)(m + 1) * vb);
     p.off_w = take((size_t)p.ld * wb);
     p.off_part = take((size_t)std::max(p.g_orth, 256) * 256 * 8);
-    p.off_part2 = take((size_t)std::max(std::max(p.g_spmv, p.g_tile), p.g_orth) * 64 * 8);
-    p.off_items = take((size_t)p.items_cap * 8);
-    p.off_lrow = take((size_t)p.long_cap * 4);
-    p.off_lfirst = take((size_t)p.long_cap * 4);
-    p.off_lnch = take((size_t)p.long_cap * 4);
-    p.off_ltk = take((size_t)p.long_cap * (size_t)K * 4);
-    p.off_lpart = take((size_t)p.items_cap * (size_t)kb2 * 8);
-    p.off_lval = take((size_t)p.long_cap * kb2 * 8);
-    p.off_scan = take((size_t)n * 8);
-    p.off_bsum = take((size_t)(ceil_div(n, 2048) + 1) * 8);
+    p.off_part2 = take((size_t)std::max(std::max(p.g_tile, p.g_orth), 2048) * 64 * 8);
+    p.off_scan = take((size_t)scan_n * 8);
+    p.off_bsum = take((size_t)(ceil_div(scan_n, 2048) + 2) * 8);
     p.off_Y = take((size_t)n * (size_t)K * 8);
+    p.off_Z = take((size_t)n * (size_t)K * 8);
     p.off_gram = take((size_t)(GRAM_PARTS + 1) * 64 * 64 * 8);
     p.off_ob = take((size_t)(p.n_tiles + 1) * 4);
     p.off_tk = take((size_t)p.n_tiles * 4);
-    p.off_head = take((size_t)p.n_tiles * 8);
-    p.off_tail = take((size_t)p.n_tiles * 8);
+    p.off_head = take((size_t)p.n_tiles * kb2 * 8);
+    p.off_tail = take((size_t)p.n_tiles * kb2 * 8);
+    p.off_rp2 = take((size_t)(n + 1) * 8);
+    p.off_col2 = take((size_t)nnz * 4);
+    p.off_val2 = take((size_t)nnz * vb);
+    p.off_perm = take((size_t)n * 4);
+    p.off_iperm = take((size_t)n * 4);
     p.bytes = o;
     return p;
 }
@@ -74,21 +71,20 @@ Bufs resolve(const Plan& p, void* base) {
     b.w = c + p.off_w;
     b.part = (double*)(c + p.off_part);
     b.part2 = (double*)(c + p.off_part2);
-    b.items = (int2*)(c + p.off_items);
-    b.lrow = (int32_t*)(c + p.off_lrow);
-    b.lfirst = (int32_t*)(c + p.off_lfirst);
-    b.lnch = (int32_t*)(c + p.off_lnch);
-    b.ltk = (uint32_t*)(c + p.off_ltk);
-    b.lpart = (double*)(c + p.off_lpart);
-    b.lval = (double*)(c + p.off_lval);
     b.scan = (uint64_t*)(c + p.off_scan);
     b.bsum = (uint64_t*)(c + p.off_bsum);
     b.Y = (double*)(c + p.off_Y);
+    b.Z = (double*)(c + p.off_Z);
     b.gram = (double*)(c + p.off_gram);
     b.ob = (int32_t*)(c + p.off_ob);
     b.tk = (uint32_t*)(c + p.off_tk);
     b.head = (double*)(c + p.off_head);
     b.tail = (double*)(c + p.off_tail);
+    b.rp2 = (int64_t*)(c + p.off_rp2);
+    b.col2 = (int32_t*)(c + p.off_col2);
+    b.val2 = c + p.off_val2;
+    b.perm = (int32_t*)(c + p.off_perm);
+    b.iperm = (int32_t*)(c + p.off_iperm);
     return b;
 }
 
@@ -119,6 +115,7 @@ void lz_options_init(lz_options* opt) {
     opt->seed = 0;
     opt->reorth = LZ_REORTH_TWICE;
     opt->report = 1;
+    opt->reorder = LZ_REORDER_AUTO;
 }
 
 const char* lz_status_string(int status) {
@@ -152,6 +149,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
     lz_options_init(&o);
     if (opt) o = *opt;
     if (o.reorth < LZ_REORTH_NONE || o.reorth > LZ_REORTH_SELECTIVE) return LZ_ERR_INVALID_ARG;
+    if (o.reorder < LZ_REORDER_OFF || o.reorder > LZ_REORDER_AUTO) return LZ_ERR_INVALID_ARG;
     const Plan p = make_plan(n, nnz, K, m, precision);
     if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
 
@@ -183,7 +181,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             for (int i = 0; i < 4; ++i) LZ_HIP(hipEventCreate(&pev[i]));
             LZ_HIP(hipEventRecord(pev[0], s));
         }
-        LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, s));
+        LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, o.reorder, s));
         LZ_HIP(launch_init(p, b, s));
         if (o.profile) LZ_HIP(hipEventRecord(pev[1], s));
         for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, s, iter_events(t)));
@@ -226,6 +224,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             report->ortho_loss = hst->ortho_loss;
             report->ritz_ortho_loss = hst->ritz_ortho_loss;
             report->mean_angle_deg = hst->mean_angle_deg;
+            report->reordered = hst->reordered;
             if (o.profile && launched > 0) {
                 float ms = 0.f;
                 double sp = 0.0, orth = 0.0;
@@ -281,7 +280,7 @@ int lz_spmv(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_v
     {
         const Bufs b = resolve(p, ws);
         const Csr a{csr_rowptr, csr_col, csr_val, n, nnz};
-        LZ_HIP(launch_setup(p, b, a, 0, LZ_REORTH_TWICE, s));
+        LZ_HIP(launch_setup(p, b, a, 0, LZ_REORTH_TWICE, LZ_REORDER_OFF, s));
         LZ_HIP(launch_spmv_plain(p, b, a, x, y, s));
         LZ_HIP(hipMemcpyAsync(&hst, b.st, sizeof(State), hipMemcpyDeviceToHost, s));
         LZ_HIP(hipStreamSynchronize(s));

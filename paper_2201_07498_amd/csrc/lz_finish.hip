@@ -234,8 +234,8 @@ __global__ __launch_bounds__(BLOCK) void k_ritz(const State* st, const typename 
     }
 }
 
-// Per Ritz column k: norm and the entry of largest modulus (lowest row on
-// ties) -> ysc[k] = sign(that entry) / norm.  Lane k of each group of KB2
+// Per Ritz column k: norm and the entry of largest modulus (lowest original
+// row on ties) -> ysc[k] = sign(that entry) / norm.  Lane k of each group of KB2
 // lanes owns column k.
 __global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __restrict__ Y, int64_t n, int KB2,
                                                     double* part) {
@@ -247,12 +247,14 @@ __global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __r
     const int groups = BLOCK / KB2, g = threadIdx.x / KB2, k = threadIdx.x % KB2;
     double nrm = 0.0, best = -1.0, bval = 0.0;
     int64_t bidx = INT64_MAX;
+    const int32_t* perm = st->perm;
     if (k < K)
         for (int64_t r = (int64_t)blockIdx.x * groups + g; r < n; r += (int64_t)G * groups) {
             const double v = Y[r * K + k];
             nrm += v * v;
             const double a = fabs(v);
-            if (a > best) { best = a; bval = v; bidx = r; }
+            const int64_t ro = perm ? perm[r] : r;
+            if (a > best || (a == best && ro < bidx)) { best = a; bval = v; bidx = ro; }
         }
     s_n[threadIdx.x] = nrm; s_a[threadIdx.x] = best; s_v[threadIdx.x] = bval; s_i[threadIdx.x] = bidx;
     __syncthreads();
@@ -295,26 +297,15 @@ __global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __r
     }
 }
 
-// Unit Ritz vectors into the caller's column-major output (no report).
-__global__ __launch_bounds__(BLOCK) void k_scale_out(const State* st, const double* __restrict__ Y, int64_t n,
-                                                     double* __restrict__ out) {
-    if (st->status != 0) return;
-    const int K = st->K;
-    const int64_t total = n * K;
-    for (int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * BLOCK) {
-        const int64_t k = idx / n, r = idx % n;
-        out[idx] = st->ysc[k] * Y[r * K + k];
-    }
-}
+// Residual check (Sec. IV-D) in FP64 for all K Ritz pairs at once.
+// First Z = A Y (stored matrix values upcast exactly) over the SpMV tiles:
+// each wavefront stages its tile's col/val in LDS; lane k of a group of KB2
+// lanes owns pair k and gathers K-wide rows of Y.  Rows are spread over the
+// 64/KB2 groups; a row longer than LONGZ, and a split row's piece, is shared
+// by all groups.  Split rows are finished by their last piece as in the
+// SpMV, the pieces added in tile order.
+constexpr int LONGZ = 32;
 
-// Residual check (Sec. IV-D) in FP64 for all K Ritz pairs at once:
-// D = A Y diag(ysc) - Y diag(ysc theta), the stored matrix values upcast
-// exactly.  Each work item's col/val pairs are staged in LDS once and used
-// for all K columns: lane k of a group of KB2 lanes owns pair k and gathers
-// K-wide rows of Y.  Rows of a row block are spread over groups (several
-// groups per row when the block has few rows); long-row chunks are split
-// over all groups and finished by the last chunk, as in the SpMV.  Writes
-// y_k to the output and sums d^2 per pair.
 // sum over p = p0, p0+step, ... < e of sval[p] * Y[scol[p]][k], with four
 // gathers in flight per lane (fixed association order).
 __device__ __forceinline__ double gather_dot(const int* scol, const double* sval, int p0, int e, int step,
@@ -335,118 +326,156 @@ __device__ __forceinline__ double gather_dot(const int* scol, const double* sval
     return (z0 + z1) + (z2 + z3);
 }
 
+// Adds the groups' values (lanes that differ in the group bits), fixed order.
+__device__ __forceinline__ double group_sum(double v, int KB2) {
+    for (int o = KB2; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_resid_mm(State* st, const int64_t* __restrict__ rp,
-                                                    const int32_t* __restrict__ col,
-                                                    const typename Tr<P>::V* __restrict__ val,
-                                                    const double* __restrict__ Y, int64_t n, int KB2,
-                                                    const int2* __restrict__ items, const int32_t* lrow,
-                                                    const int32_t* lfirst, const int32_t* lnch, uint32_t* ltk,
-                                                    double* lpart, double* lval, double* part,
-                                                    double* __restrict__ out) {
-    __shared__ int scol[2 * NB];
-    __shared__ double sval[2 * NB];
+__global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restrict__ Y, double* __restrict__ Z,
+                                                int64_t n, int64_t nnz, int64_t n_tiles, const int32_t* __restrict__ ob,
+                                                uint32_t* tk, double* head, double* tail, int KB2) {
+    using VT = typename Tr<P>::V;
+    __shared__ int scol_all[WAVES][TILE];
+    __shared__ double sval_all[WAVES][TILE];
+    if (st->status != 0) return;
+    const int64_t* rp = st->crp;
+    const int32_t* col = st->ccol;
+    const VT* val = (const VT*)st->cval;
+    const int K = st->K;
+    const int lane = threadIdx.x & 63;
+    const int G = 64 / KB2, g = lane / KB2, k = lane % KB2;
+    const bool act = k < K;
+    int* scol = scol_all[threadIdx.x >> 6];
+    double* sval = sval_all[threadIdx.x >> 6];
+    // Pieces of split row r (tail pieces in t1..t2-1, head piece in t2),
+    // added group-strided in tile order; the whole row sum in every group.
+    auto split_total_k = [&](int64_t t1, int64_t t2) {
+        double z = 0.0;
+        if (act)
+            for (int64_t i = t1 + g; i < t2; i += G) z += ld_dev(&tail[i * KB2 + k]);
+        z = group_sum(z, KB2);
+        return act ? z + ld_dev(&head[t2 * KB2 + k]) : 0.0;
+    };
+    const TileRange tr = wave_tiles(n_tiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
+        const int64_t r_lo = ob[t], r_hi = ob[t + 1];
+        const int64_t t0 = t * TILE - r_lo;
+        const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
+        for (int i = lane; i < cnt; i += 64) {
+            scol[i] = col[t0 + i];
+            sval[i] = to_d(val[t0 + i]);
+        }
+        wave_sync();
+        const bool split_head = r_lo < r_hi && rp[r_lo] < t0;
+        double head_z = 0.0;
+        for (int64_t base = r_lo; base < r_hi; base += G) {
+            const int64_t r = base + g;
+            const bool valid = r < r_hi;
+            int b = 0, e = 0;
+            if (valid) {
+                b = (int)(max(rp[r], t0) - t0);
+                e = (int)(rp[r + 1] - t0);
+            }
+            const bool islong = valid && e - b > LONGZ;
+            double z = (valid && !islong && act) ? gather_dot(scol, sval, b, e, 1, Y, K, k) : 0.0;
+            uint64_t mask = __ballot(islong && k == 0);
+            while (mask) {
+                const int L = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int bL = __shfl(b, L, 64), eL = __shfl(e, L, 64);
+                double zz = act ? gather_dot(scol, sval, bL + g, eL, G, Y, K, k) : 0.0;
+                zz = group_sum(zz, KB2);
+                if (g == L / KB2) z = zz;
+            }
+            if (valid && act) {
+                if (split_head && r == r_lo)
+                    head_z = z;
+                else
+                    Z[r * K + k] = z;
+            }
+        }
+        if (split_head) {
+            if (g == 0 && act) st_dev(&head[t * KB2 + k], head_z);
+            const int64_t t1 = item_tile(rp[r_lo] + r_lo, n_tiles);
+            if (last_wave(&tk[t], (uint32_t)(t - t1 + 1))) {
+                const double z = split_total_k(t1, t);
+                if (g == 0 && act) Z[r_lo * K + k] = z;
+            }
+        }
+        if (r_hi < n) {
+            const int64_t rb = rp[r_hi];
+            if (rb < t0 + cnt) {
+                double zz = act ? gather_dot(scol, sval, (int)(max(rb, t0) - t0) + g, cnt, G, Y, K, k) : 0.0;
+                zz = group_sum(zz, KB2);
+                if (g == 0 && act) st_dev(&tail[t * KB2 + k], zz);
+                const int64_t t1 = item_tile(rb + r_hi, n_tiles), t2 = row_owner(rp, r_hi, n_tiles);
+                if (last_wave(&tk[t2], (uint32_t)(t2 - t1 + 1))) {
+                    const double z = split_total_k(t1, t2);
+                    if (g == 0 && act) Z[r_hi * K + k] = z;
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+// Unit Ritz vectors y_k = ysc_k Y[:,k] into the caller's column-major output
+// in original row order (a 64-row block is gathered row-wise and written
+// column-wise through LDS) and, with the report, the residuals
+// ||A y_k - theta_k y_k|| = ||ysc_k Z[:,k] - theta_k y_k||, summed per pair
+// in a fixed order.
+__global__ __launch_bounds__(BLOCK) void k_resid_out(State* st, const double* __restrict__ Y,
+                                                     const double* __restrict__ Z, int64_t n, int KB2, int report,
+                                                     double* part, double* __restrict__ out) {
+    __shared__ double ys[64][65];
     __shared__ double shz[BLOCK];
     __shared__ double red[4][64];
     __shared__ int s_last;
     if (st->status != 0) return;
     const int K = st->K;
-    const int tid = threadIdx.x;
-    const int groups = BLOCK / KB2, g = tid / KB2, k = tid % KB2;
+    const int tid = threadIdx.x, k = tid % KB2;
     const bool act = k < K;
     const double ysc = act ? st->ysc[k] : 0.0;
     const double th = act ? st->theta[st->sel[k]] : 0.0;
+    const int32_t* iperm = st->iperm;
     double racc = 0.0;
-    auto finalize = [&](int64_t r, double z) -> double {
-        const double y = ysc * Y[r * K + k];
-        out[(int64_t)k * n + r] = y;
-        const double d = ysc * z - th * y;
-        return d * d;
-    };
-    const int nitems = st->n_items;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const int2 item = items[it];
-        if (item.x >= 0) {
-            const int64_t rs = item.x, re = item.y;
-            const int64_t ps = rp[rs];
-            const int cnt = (int)min<int64_t>(rp[re] - ps, 2 * NB);
-            for (int t = tid; t < cnt; t += BLOCK) {
-                scol[t] = col[ps + t];
-                sval[t] = to_d(val[ps + t]);
-            }
-            __syncthreads();
-            const int nr = (int)(re - rs);
-            int gpr = 1;
-            while (gpr < groups && gpr * 2 * nr <= groups) gpr <<= 1;
-            const int per_round = groups / gpr, slot = g / gpr, sub = g % gpr;
-            for (int row0 = 0; row0 < nr; row0 += per_round) {
-                const int row = row0 + slot;
-                double z = 0.0;
-                if (row < nr && act) {
-                    const int b = (int)(rp[rs + row] - ps), e = (int)(rp[rs + row + 1] - ps);
-                    z = gather_dot(scol, sval, b + sub, e, gpr, Y, K, k);
-                }
-                if (gpr > 1) {
-                    shz[tid] = z;
-                    __syncthreads();
-                    if (sub == 0) {
-                        z = 0.0;
-                        for (int s2 = 0; s2 < gpr; ++s2) z += shz[(slot * gpr + s2) * KB2 + k];
-                    }
-                    __syncthreads();
-                }
-                if (sub == 0 && row < nr && act) racc += finalize(rs + row, z);
-            }
-            __syncthreads();
-        } else {
-            const int lid = -1 - item.x;
-            const int64_t r = lrow[lid];
-            const int64_t p0 = rp[r] + (int64_t)item.y * CH;
-            const int cnt = (int)(min(p0 + (int64_t)CH, rp[r + 1]) - p0);
-            double z = 0.0;
-            for (int base = 0; base < cnt; base += 2 * NB) {
-                const int c2 = min(cnt - base, 2 * NB);
-                for (int t = tid; t < c2; t += BLOCK) {
-                    scol[t] = col[p0 + base + t];
-                    sval[t] = to_d(val[p0 + base + t]);
-                }
-                __syncthreads();
-                if (act) z += gather_dot(scol, sval, g, c2, groups, Y, K, k);
-                __syncthreads();
-            }
-            shz[tid] = z;
-            __syncthreads();
-            if (g == 0 && act) {
-                double zs = 0.0;
-                for (int gg = 0; gg < groups; ++gg) zs += shz[gg * KB2 + k];
-                st_dev(&lpart[(int64_t)it * KB2 + k], zs);
-            }
-            if (last_block(&ltk[lid], (uint32_t)lnch[lid], &s_last)) {
-                if (g == 0 && act) {
-                    const int f = lfirst[lid], nc = lnch[lid];
-                    double tot = 0.0;
-                    for (int q = 0; q < nc; ++q) tot += ld_dev(&lpart[(int64_t)(f + q) * KB2 + k]);
-                    st_dev(&lval[(int64_t)lid * KB2 + k], finalize(r, tot));
+    for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < n; r0 += (int64_t)gridDim.x * 64) {
+        for (int idx = tid; idx < 64 * KB2; idx += BLOCK) {
+            const int row = idx / KB2;
+            const int64_t r = r0 + row;
+            if (r < n && act) {
+                const int64_t i = iperm ? iperm[r] : r;
+                const double y = ysc * Y[i * K + k];
+                ys[row][k] = y;
+                if (report) {
+                    const double d = ysc * Z[i * K + k] - th * y;
+                    racc += d * d;
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
+        for (int idx = tid; idx < 64 * K; idx += BLOCK) {
+            const int kk = idx / 64, row = idx % 64;
+            const int64_t r = r0 + row;
+            if (r < n) out[(int64_t)kk * n + r] = ys[row][kk];
+        }
+        __syncthreads();
     }
+    if (!report) return;
     shz[tid] = racc;
     __syncthreads();
     if (tid < KB2) {
         double s = 0.0;
-        for (int gg = 0; gg < groups; ++gg) s += shz[gg * KB2 + tid];
+        for (int gg = 0; gg < BLOCK / KB2; ++gg) s += shz[gg * KB2 + tid];
         st_dev(&part[(int64_t)blockIdx.x * 64 + tid], s);
     }
     if (last_block(&st->ticket[TK_RESID], gridDim.x, &s_last)) {
-        const int nl = st->n_long, G = gridDim.x;
         const int q = tid >> 6, l = tid & 63;
         double s = 0.0;
-        if (l < K) {
-            for (int b = q; b < G; b += 4) s += ld_dev(&part[(int64_t)b * 64 + l]);
-            for (int i = q; i < nl; i += 4) s += ld_dev(&lval[(int64_t)i * KB2 + l]);
-        }
+        if (l < K)
+            for (int b = q; b < (int)gridDim.x; b += 4) s += ld_dev(&part[(int64_t)b * 64 + l]);
         red[q][l] = s;
         __syncthreads();
         if (q == 0 && l < K) {
@@ -618,13 +647,13 @@ static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* o
     const int kb2 = pow2_at_least(p.K);
     const int gc = (int)std::max<int64_t>(1, std::min<int64_t>(256, (p.n * kb2 + BLOCK - 1) / BLOCK));
     hipLaunchKernelGGL(k_colstats, dim3(gc), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, b.part);
-    if (!report) {
-        const int go = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (p.n * p.K + BLOCK - 1) / BLOCK));
-        hipLaunchKernelGGL(k_scale_out, dim3(go), dim3(BLOCK), 0, s, b.st, b.Y, p.n, out_vecs);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_resid_mm<P>), dim3(p.g_spmv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, (const VT*)a.val,
-                       b.Y, p.n, kb2, b.items, b.lrow, b.lfirst, b.lnch, b.ltk, b.lpart, b.lval, b.part2, out_vecs);
+    if (report)
+        hipLaunchKernelGGL((k_spmm<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, b.Y, b.Z, p.n, p.nnz, p.n_tiles,
+                           b.ob, b.tk, b.head, b.tail, kb2);
+    const int go = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (p.n + 63) / 64));
+    hipLaunchKernelGGL(k_resid_out, dim3(go), dim3(BLOCK), 0, s, b.st, b.Y, b.Z, p.n, kb2, report, b.part2,
+                       out_vecs);
+    if (!report) return hipGetLastError();
     const int gg = gram_grid(p.n);
     double* G = b.gram + (int64_t)GRAM_PARTS * 4096;
     hipLaunchKernelGGL((k_gram<VT, false>), dim3(gg), dim3(BLOCK), 0, s, b.st, V, p.ld, p.n, 0, b.gram);

@@ -13,9 +13,6 @@ namespace lz {
 constexpr int MMAX = 64;       // largest m (Lanczos steps); Jacobi tile in LDS
 constexpr int NCMAX = 72;      // column bound of the orthogonalisation kernels (m+1 rounded to 8)
 constexpr int BLOCK = 256;     // threads per workgroup (4 wave64)
-constexpr int NB = 256;        // target non-zeros per row-block work item (one wavefront)
-constexpr int CH = 2048;       // non-zeros per chunk of a long row
-constexpr int RMAX = 64;       // rows per row-block work item at most
 constexpr int TILE = 1024;     // non-zeros per SpMV tile (one wavefront, 16 per lane)
 constexpr int LDPAD = 2048;    // basis leading dimension is a multiple of this
 constexpr int OGRID = 1024;    // orthogonalisation grid cap (workgroups)
@@ -43,6 +40,14 @@ struct State {
     double u_s;           // unit roundoff of the stored basis
     double tnorm;         // max_j (|alpha_j| + beta_j), scales the breakdown threshold
     double wnorm2;        // ||w'||^2 after the first update (selective second pass)
+    // Matrix of the solve: the caller's CSR or its hub-first relabelling.
+    const int64_t* crp;
+    const int32_t* ccol;
+    const void* cval;
+    const int32_t* perm;       // relabelled row -> original row (null: identity)
+    const int32_t* iperm;      // original row -> relabelled row
+    int32_t reorder, reordered;
+    unsigned long long maxdeg; // longest row of the input
     double alpha[MMAX + 8];
     double beta[MMAX + 8];     // beta[k] couples columns k-1 and k; beta[0] = 0
     double scale[MMAX + 8];
@@ -60,12 +65,11 @@ struct State {
 struct Plan {
     int64_t n = 0, nnz = 0, ld = 0;
     int32_t K = 0, m = 0, prec = 0, KB = 0;
-    int32_t g_spmv = 0, g_orth = 0, g_tile = 0;
-    int64_t items_cap = 0, long_cap = 0, n_tiles = 0;
-    size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_items = 0,
-           off_lrow = 0, off_lfirst = 0, off_lnch = 0, off_ltk = 0, off_lpart = 0, off_lval = 0,
-           off_scan = 0, off_bsum = 0, off_Y = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0,
-           off_tail = 0;
+    int32_t g_orth = 0, g_tile = 0;
+    int64_t n_tiles = 0;
+    size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
+           off_Y = 0, off_Z = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0, off_tail = 0, off_rp2 = 0,
+           off_col2 = 0, off_val2 = 0, off_perm = 0, off_iperm = 0;
     size_t bytes = 0;
 };
 
@@ -83,22 +87,21 @@ struct Bufs {
     void* V;
     void* w;
     double* part;      // per-workgroup partials: max(g_orth, 256) * 256 doubles
-    double* part2;     // second partial buffer (SpMV long rows, residual)
-    int2* items;
-    int32_t* lrow;
-    int32_t* lfirst;
-    int32_t* lnch;
-    uint32_t* ltk;
-    double* lpart;     // long-row chunk partials (items_cap * KB)
-    double* lval;      // per-long-row epilogue values (long_cap * KB)
-    uint64_t* scan;
-    uint64_t* bsum;
-    double* Y;         // Ritz vectors, column-major n x K, before normalisation
+    double* part2;     // second partial buffer (SpMV alpha, residual)
+    uint64_t* scan;    // scan scratch (degree-class histogram)
+    uint64_t* bsum;    // scan block sums
+    double* Y;         // Ritz vectors, row-major n x K, before normalisation
+    double* Z;         // A Y, row-major n x K (residual check)
     double* gram;      // Gram partials (GRAM_PARTS x 64 x 64), then the reduced 64 x 64
     int32_t* ob;       // SpMV tiles: first owned row of every tile (n_tiles + 1)
     uint32_t* tk;      // split-row tickets, one per owner tile
-    double* head;      // split-row pieces at the start of a tile
-    double* tail;      // split-row pieces at the end of a tile
+    double* head;      // split-row pieces at the start of a tile (n_tiles x KB2)
+    double* tail;      // split-row pieces at the end of a tile (n_tiles x KB2)
+    int64_t* rp2;      // hub-first relabelled CSR
+    int32_t* col2;
+    void* val2;
+    int32_t* perm;
+    int32_t* iperm;
 };
 Bufs resolve(const Plan& p, void* base);
 
@@ -111,7 +114,7 @@ struct Csr {
 };
 
 // ------------------------------------------------------------- launchers
-hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth,
+hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth, int reorder,
                         hipStream_t s);
 hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s);
 // One Lanczos iteration (SpMV or restart draw, two CGS passes, store).

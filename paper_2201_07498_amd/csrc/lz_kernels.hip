@@ -1,5 +1,5 @@
 // gfx950 kernels of one Lanczos iteration (Sec. II, Algorithm 1) and the
-// per-matrix setup.
+// start vector.
 //
 // One iteration is four kernels:
 //   k_spmv_step      w = A v_j - beta_j v_{j-1};  alpha_j = v_j . (A v_j)
@@ -20,204 +20,10 @@
 
 namespace lz {
 
-// ------------------------------------------------------------------ state
-__global__ void k_reset(State* st, int m, int K, int reorth, double u_s, uint64_t seed) {
-    uint64_t* p = reinterpret_cast<uint64_t*>(st);
-    const size_t words = sizeof(State) / 8;
-    for (size_t i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0ull;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        st->m = m;
-        st->K = K;
-        st->reorth = reorth;
-        st->u_s = u_s;
-        st->seed = seed;
-    }
-}
-
-// Input checks before any kernel indexes memory through the CSR arrays:
-// rowptr[0] = 0, rowptr[n] = nnz, rows non-decreasing, 0 <= col < n.
-__global__ __launch_bounds__(BLOCK) void k_validate(State* st, const int64_t* rp, const int32_t* col, int64_t n,
-                                                    int64_t nnz) {
-    bool bad = false;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    const int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t0 == 0) bad |= (rp[0] != 0) || (rp[n] != nnz);
-    for (int64_t r = t0; r < n; r += stride) bad |= rp[r + 1] < rp[r];
-    for (int64_t p = t0; p < nnz; p += stride) bad |= (col[p] < 0) || ((int64_t)col[p] >= n);
-    if (bad) __hip_atomic_store(&st->status, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ------------------------------------------------------ matrix partition
-// Row r starts a new work item when it is the first row, a multiple of RMAX,
-// long, after a long row, or when a multiple of NB lies between the start of
-// row r-1 and the start of row r.  A row block therefore holds fewer than
-// NB + (its last row's length) <= 2*NB non-zeros.
-__device__ __forceinline__ bool row_starts_item(const int64_t* rp, int64_t r) {
-    if (r == 0 || (r % RMAX) == 0) return true;
-    const int64_t b = rp[r];
-    if (rp[r + 1] - b > NB) return true;
-    const int64_t a = rp[r - 1];
-    if (b - a > NB) return true;
-    return (a / NB) != (b / NB);
-}
-
-constexpr uint64_t LOW40 = (1ull << 40) - 1ull;
-
-// Packed per-row count: items in the low 40 bits, long rows above.
-__device__ __forceinline__ uint64_t item_count(const int64_t* rp, int64_t r) {
-    if (!row_starts_item(rp, r)) return 0ull;
-    const int64_t len = rp[r + 1] - rp[r];
-    if (len > NB) return (uint64_t)((len + CH - 1) / CH) | (1ull << 40);
-    return 1ull;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_setup_count(const int64_t* rp, int64_t n, uint64_t* cnt) {
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLOCK)
-        cnt[r] = item_count(rp, r);
-}
-
-constexpr int SCAN_PER = 8;
-constexpr int SCAN_TILE = BLOCK * SCAN_PER;
-
-__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* sh, uint64_t* total) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < BLOCK; o <<= 1) {
-        const uint64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0ull;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
-    }
-    const uint64_t incl = sh[threadIdx.x];
-    *total = sh[BLOCK - 1];
-    __syncthreads();
-    return incl - v;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint64_t* x, int64_t n, uint64_t* bsum) {
-    __shared__ uint64_t sh[BLOCK];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    uint64_t s = 0;
-    for (int i = 0; i < SCAN_PER; ++i) {
-        const int64_t r = base + (int64_t)threadIdx.x * SCAN_PER + i;
-        if (r < n) s += x[r];
-    }
-    uint64_t tot;
-    block_exclusive_scan(s, sh, &tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-// Exclusive scan of nb block sums in place (one workgroup); bsum[nb] = total.
-__global__ __launch_bounds__(BLOCK) void k_scan_top(uint64_t* bsum, int64_t nb) {
-    __shared__ uint64_t sh[BLOCK];
-    const int64_t per = (nb + BLOCK - 1) / BLOCK;
-    const int64_t b0 = (int64_t)threadIdx.x * per;
-    uint64_t s = 0;
-    for (int64_t i = 0; i < per; ++i)
-        if (b0 + i < nb) s += bsum[b0 + i];
-    uint64_t tot;
-    uint64_t run = block_exclusive_scan(s, sh, &tot);
-    for (int64_t i = 0; i < per; ++i)
-        if (b0 + i < nb) {
-            const uint64_t v = bsum[b0 + i];
-            bsum[b0 + i] = run;
-            run += v;
-        }
-    if (threadIdx.x == 0) bsum[nb] = tot;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_apply(uint64_t* x, int64_t n, const uint64_t* bsum) {
-    __shared__ uint64_t sh[BLOCK];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER;
-    uint64_t v[SCAN_PER];
-    uint64_t s = 0;
-    for (int i = 0; i < SCAN_PER; ++i) {
-        v[i] = (base + i < n) ? x[base + i] : 0ull;
-        s += v[i];
-    }
-    uint64_t tot;
-    uint64_t run = block_exclusive_scan(s, sh, &tot) + bsum[blockIdx.x];
-    for (int i = 0; i < SCAN_PER; ++i)
-        if (base + i < n) {
-            x[base + i] = run;
-            run += v[i];
-        }
-}
-
-// Writes the items (row blocks get their end row in k_setup_ends) and the
-// long-row tables; clears `kslices` ticket slices per long row.
-__global__ __launch_bounds__(BLOCK) void k_setup_items(const int64_t* rp, int64_t n, const uint64_t* off,
-                                                       const uint64_t* total, int64_t items_cap,
-                                                       int64_t long_cap, int kslices, int2* items, int32_t* lrow,
-                                                       int32_t* lfirst, int32_t* lnch, uint32_t* ltk, State* st) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint64_t t = *total;
-        const int64_t ni = (int64_t)(t & LOW40), nl = (int64_t)(t >> 40);
-        if (ni > items_cap || nl > long_cap) {
-            st->status = -4;   // LZ_ERR_WORKSPACE_TOO_SMALL
-            st->n_items = 0;
-            st->n_long = 0;
-        } else {
-            st->n_items = (int32_t)ni;
-            st->n_long = (int32_t)nl;
-        }
-    }
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLOCK) {
-        if (!row_starts_item(rp, r)) continue;
-        const uint64_t o = off[r];
-        const int64_t first = (int64_t)(o & LOW40);
-        const int64_t lid = (int64_t)(o >> 40);
-        const int64_t len = rp[r + 1] - rp[r];
-        if (len > NB) {
-            const int64_t nch = (len + CH - 1) / CH;
-            if (first + nch > items_cap || lid >= long_cap) continue;
-            for (int64_t c = 0; c < nch; ++c) items[first + c] = make_int2((int)(-1 - lid), (int)c);
-            lrow[lid] = (int32_t)r;
-            lfirst[lid] = (int32_t)first;
-            lnch[lid] = (int32_t)nch;
-            for (int k = 0; k < kslices; ++k) ltk[(int64_t)k * long_cap + lid] = 0u;
-        } else {
-            if (first >= items_cap) continue;
-            items[first] = make_int2((int)r, -1);
-        }
-    }
-}
-
-// A row block ends where the next item starts.
-__global__ __launch_bounds__(BLOCK) void k_setup_ends(const State* st, int64_t n, int2* items, const int32_t* lrow) {
-    const int ni = st->n_items;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < ni; i += gridDim.x * BLOCK) {
-        const int2 it = items[i];
-        if (it.x < 0) continue;
-        int end = (int)n;
-        if (i + 1 < ni) {
-            const int2 nx = items[i + 1];
-            end = nx.x >= 0 ? nx.x : lrow[-1 - nx.x];
-        }
-        items[i].y = end;
-    }
-}
-
-// Tile table: ob[t] = first row owned by tile t, ob[n_tiles] = n; clears the
-// split-row tickets.  Owners are non-decreasing in r, so row r writes the
-// entries of the tiles between its predecessor's owner and its own.
-__global__ __launch_bounds__(BLOCK) void k_setup_tiles(const int64_t* rp, int64_t n, int64_t n_tiles, int32_t* ob,
-                                                       uint32_t* tk) {
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    const int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    for (int64_t t = t0; t < n_tiles; t += stride) tk[t] = 0u;
-    if (t0 == 0) ob[n_tiles] = (int32_t)n;
-    for (int64_t r = t0; r < n; r += stride) {
-        const int64_t own = row_owner(rp, r, n_tiles);
-        const int64_t prev = r > 0 ? row_owner(rp, r - 1, n_tiles) : -1;
-        for (int64_t t = prev + 1; t <= own; ++t) ob[t] = (int32_t)r;
-    }
-}
-
 // ------------------------------------------------------------ start vector
-// V[:,0] = u rounded to the basis precision, u_r = U01(SplitMix64(seed, r));
-// scale[0] = 1/||stored u||.  Also clears w (its padding rows must stay zero).
+// V[:,0] = u rounded to the basis precision, u_r = U01(SplitMix64(seed, r))
+// with r the original row index; scale[0] = 1/||stored u||.  Also clears w
+// (its padding rows must stay zero).
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_init(State* st, typename Tr<P>::V* V, typename Tr<P>::W* w,
                                                 int64_t n, int64_t ld, double* part) {
@@ -230,9 +36,10 @@ __global__ __launch_bounds__(BLOCK) void k_init(State* st, typename Tr<P>::V* V,
         return;
     }
     const uint64_t seed = st->seed;
+    const int32_t* perm = st->perm;
     double s = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < ld; r += (int64_t)gridDim.x * BLOCK) {
-        const VT v = from_d<VT>(r < n ? u01(seed, (uint64_t)r) : 0.0);
+        const VT v = from_d<VT>(r < n ? u01(seed, (uint64_t)(perm ? perm[r] : r)) : 0.0);
         V[r] = v;
         w[r] = (WT)0;
         const double d = to_d(v);
@@ -257,10 +64,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(State* st, typename Tr<P>::V* V,
 // alpha_j = v_j . y.  In a restart iteration it draws the restart vector
 // into w instead.
 template <int P>
-__global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const int64_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ col,
-                                                     const typename Tr<P>::V* __restrict__ val,
-                                                     const typename Tr<P>::V* __restrict__ Vb,
+__global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                      typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
                                                      int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
                                                      uint32_t* tk, double* head, double* tail, double* part) {
@@ -276,10 +80,14 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const int64_t* _
         // Restart: a fresh random vector; the Gram-Schmidt kernels that follow
         // orthogonalise it against the basis.
         const uint64_t rs = st->seed + ((uint64_t)st->restarts << 32);
+        const int32_t* perm = st->perm;
         for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < ld; r += (int64_t)gridDim.x * BLOCK)
-            w[r] = (WT)(r < n ? u01(rs, (uint64_t)r) : 0.0);
+            w[r] = (WT)(r < n ? u01(rs, (uint64_t)(perm ? perm[r] : r)) : 0.0);
         return;
     }
+    const int64_t* rp = st->crp;
+    const int32_t* col = st->ccol;
+    const VT* val = (const VT*)st->cval;
     const VT* x = Vb + (int64_t)j * ld;
     const VT* xp = j > 0 ? Vb + (int64_t)(j - 1) * ld : nullptr;
     const double sj = st->scale[j];
@@ -720,8 +528,8 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
     VT* V = (VT*)b.V;
     WT* w = (WT*)b.w;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL((k_spmv_step<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, (const VT*)a.val,
-                       V, w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+    hipLaunchKernelGGL((k_spmv_step<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, V, w, a.n, a.nnz, p.ld,
+                       p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
     if (ev) (void)hipEventRecord(ev[1], s);
     const int nb = nc_bucket(ncols);
 #define LZ_ORTH_CASE(NCV)                                                                                  \
@@ -758,25 +566,6 @@ hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncol
         case 2: return iteration_p<2>(p, b, a, ncols, s, ev);
     }
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, b.st, p.m, p.K, reorth, unit_roundoff(p.prec), seed);
-    const int64_t n = a.n;
-    const int g = (int)std::min<int64_t>((n + BLOCK - 1) / BLOCK, 8192);
-    const int gv = (int)std::min<int64_t>((std::max(n, a.nnz) + BLOCK - 1) / BLOCK, 8192);
-    hipLaunchKernelGGL(k_validate, dim3(gv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, n, a.nnz);
-    hipLaunchKernelGGL(k_setup_count, dim3(g), dim3(BLOCK), 0, s, a.rowptr, n, b.scan);
-    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(BLOCK), 0, s, b.scan, n, b.bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, b.bsum, nb);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(BLOCK), 0, s, b.scan, n, b.bsum);
-    hipLaunchKernelGGL(k_setup_items, dim3(g), dim3(BLOCK), 0, s, a.rowptr, n, b.scan, b.bsum + nb, p.items_cap,
-                       p.long_cap, p.K, b.items, b.lrow, b.lfirst, b.lnch, b.ltk, b.st);
-    const int gi = (int)std::min<int64_t>((p.items_cap + BLOCK - 1) / BLOCK, 4096);
-    hipLaunchKernelGGL(k_setup_ends, dim3(gi), dim3(BLOCK), 0, s, b.st, n, b.items, b.lrow);
-    hipLaunchKernelGGL(k_setup_tiles, dim3(g), dim3(BLOCK), 0, s, a.rowptr, n, p.n_tiles, b.ob, b.tk);
-    return hipGetLastError();
 }
 
 hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s) {

@@ -183,7 +183,7 @@ hipError_t Server::launch_lanczos(Slot& s) {
     const Plan& p = s.req->plan;
     const lz_request& r = s.req->r;
     auto body = [&]() -> hipError_t {
-        hipError_t e = launch_setup(p, s.bufs, s.csr, r.seed, r.reorth, s.stream);
+        hipError_t e = launch_setup(p, s.bufs, s.csr, r.seed, r.reorth, LZ_REORDER_AUTO, s.stream);
         if (e == hipSuccess) e = launch_init(p, s.bufs, s.stream);
         for (int t = 0; t < p.m && e == hipSuccess; ++t) e = launch_iteration(p, s.bufs, s.csr, t + 1, s.stream);
         return e;

@@ -1,0 +1,355 @@
+// Per-matrix setup of a solve on gfx950: input checks, the optional
+// hub-first relabelling of the matrix and the SpMV tile table.
+//
+// Hub-first relabelling.  Algorithm 1 runs unchanged on P A P^T for a
+// permutation P; its Ritz values are those of A and its Ritz vectors are
+// P y.  On power-law graphs most gathers of x hit a few high-degree
+// vertices, and listing those vertices first packs the hot part of x into
+// few cache lines (it stays in L1/L2 instead of crossing the fabric).  The
+// permutation is a stable counting sort of the rows by degree class
+// (half-octaves of degree + 1, largest first), so rows of one class keep
+// their original order.  Everything random the method draws (start and
+// restart vectors) is drawn by original row index, and the Ritz vectors are
+// written back in original order, so the Krylov sequence is the one of the
+// original problem up to rounding.
+//
+// The decision is taken on the device (the caller's stream never waits for
+// the host): with LZ_REORDER_AUTO the matrix is relabelled when it is large
+// and skewed (n >= REORDER_MIN_N and the longest row at least REORDER_SKEW
+// times the mean row length).
+#include <algorithm>
+
+#include "../../include/lanczos_topk.h"
+#include "lz_spmv.h"
+
+namespace lz {
+
+constexpr int64_t REORDER_MIN_N = 1 << 17;
+constexpr double REORDER_SKEW = 32.0;
+constexpr int CHR = 4096;          // rows per counting-sort chunk (one workgroup)
+constexpr int NKEY = 64;           // degree classes
+
+__global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double u_s, uint64_t seed) {
+    uint64_t* p = reinterpret_cast<uint64_t*>(st);
+    const size_t words = sizeof(State) / 8;
+    for (size_t i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0ull;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->m = m;
+        st->K = K;
+        st->reorth = reorth;
+        st->reorder = reorder;
+        st->u_s = u_s;
+        st->seed = seed;
+    }
+}
+
+// Input checks before any kernel indexes memory through the CSR arrays:
+// rowptr[0] = 0, rowptr[n] = nnz, rows non-decreasing, 0 <= col < n.  Also
+// finds the longest row.
+__global__ __launch_bounds__(BLOCK) void k_validate(State* st, const int64_t* rp, const int32_t* col, int64_t n,
+                                                    int64_t nnz) {
+    bool bad = false;
+    uint64_t mx = 0;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t0 == 0) bad |= (rp[0] != 0) || (rp[n] != nnz);
+    for (int64_t r = t0; r < n; r += stride) {
+        const int64_t d = rp[r + 1] - rp[r];
+        bad |= d < 0;
+        mx = d > 0 && (uint64_t)d > mx ? (uint64_t)d : mx;
+    }
+    for (int64_t p = t0; p < nnz; p += stride) bad |= (col[p] < 0) || ((int64_t)col[p] >= n);
+    if (bad) __hip_atomic_store(&st->status, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t v = __shfl_xor(mx, o, 64);
+        mx = v > mx ? v : mx;
+    }
+    if ((threadIdx.x & 63) == 0 && mx > 0)
+        __hip_atomic_fetch_max(&st->maxdeg, (unsigned long long)mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Chooses the matrix of the solve and publishes its pointers in the state.
+__global__ void k_reorder_decide(State* st, const int64_t* rp, const int32_t* col, const void* val, int64_t n,
+                                 int64_t nnz, int64_t* rp2, int32_t* col2, void* val2, int32_t* perm,
+                                 int32_t* iperm) {
+    if (threadIdx.x != 0) return;
+    const int opt = st->reorder;
+    bool use = false;
+    if (st->status == 0 && n > 1 && nnz > 0) {
+        if (opt == LZ_REORDER_HUBS) use = true;
+        if (opt == LZ_REORDER_AUTO)
+            use = n >= REORDER_MIN_N && (double)st->maxdeg * (double)n >= REORDER_SKEW * (double)nnz;
+    }
+    st->reordered = use ? 1 : 0;
+    st->crp = use ? rp2 : rp;
+    st->ccol = use ? col2 : col;
+    st->cval = use ? val2 : val;
+    st->perm = use ? perm : nullptr;
+    st->iperm = use ? iperm : nullptr;
+}
+
+// ------------------------------------------------------------- scans
+constexpr int SCAN_PER = 8;
+constexpr int SCAN_TILE = BLOCK * SCAN_PER;
+
+__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* sh, uint64_t* total) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < BLOCK; o <<= 1) {
+        const uint64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0ull;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const uint64_t incl = sh[threadIdx.x];
+    *total = sh[BLOCK - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// Exclusive scan of x[0..n) in place, in three kernels; skipped unless
+// *gate is set.
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int32_t* gate, const uint64_t* x, int64_t n,
+                                                       uint64_t* bsum) {
+    __shared__ uint64_t sh[BLOCK];
+    if (!*gate) return;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint64_t s = 0;
+    for (int i = 0; i < SCAN_PER; ++i) {
+        const int64_t r = base + (int64_t)threadIdx.x * SCAN_PER + i;
+        if (r < n) s += x[r];
+    }
+    uint64_t tot;
+    block_exclusive_scan(s, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_top(const int32_t* gate, uint64_t* bsum, int64_t nb) {
+    __shared__ uint64_t sh[BLOCK];
+    if (!*gate) return;
+    const int64_t per = (nb + BLOCK - 1) / BLOCK;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    uint64_t s = 0;
+    for (int64_t i = 0; i < per; ++i)
+        if (b0 + i < nb) s += bsum[b0 + i];
+    uint64_t tot;
+    uint64_t run = block_exclusive_scan(s, sh, &tot);
+    for (int64_t i = 0; i < per; ++i)
+        if (b0 + i < nb) {
+            const uint64_t v = bsum[b0 + i];
+            bsum[b0 + i] = run;
+            run += v;
+        }
+    if (threadIdx.x == 0) bsum[nb] = tot;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(const int32_t* gate, uint64_t* x, int64_t n,
+                                                      const uint64_t* bsum) {
+    __shared__ uint64_t sh[BLOCK];
+    if (!*gate) return;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER;
+    uint64_t v[SCAN_PER];
+    uint64_t s = 0;
+    for (int i = 0; i < SCAN_PER; ++i) {
+        v[i] = (base + i < n) ? x[base + i] : 0ull;
+        s += v[i];
+    }
+    uint64_t tot;
+    uint64_t run = block_exclusive_scan(s, sh, &tot) + bsum[blockIdx.x];
+    for (int i = 0; i < SCAN_PER; ++i)
+        if (base + i < n) {
+            x[base + i] = run;
+            run += v[i];
+        }
+}
+
+static void scan(const int32_t* gate, uint64_t* x, int64_t n, uint64_t* bsum, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, (n + SCAN_TILE - 1) / SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(BLOCK), 0, s, gate, x, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, gate, bsum, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(BLOCK), 0, s, gate, x, n, bsum);
+}
+
+// ------------------------------------------------------- relabelling
+// Degree class: 63 - floor(log2((d+1)^2)), so longer rows sort first.
+__device__ __forceinline__ int degree_key(int64_t d) {
+    uint64_t x = (uint64_t)min<int64_t>(d, (int64_t(1) << 31) - 1) + 1u;
+    x *= x;
+    return __builtin_clzll(x);       // = 63 - floor(log2 x), in [2, 63]
+}
+
+// hist[key * nch + c] = rows of class key in chunk c.
+__global__ __launch_bounds__(BLOCK) void k_rl_hist(const State* st, const int64_t* rp, int64_t n, int64_t nch,
+                                                   uint64_t* hist) {
+    __shared__ uint32_t cnt[NKEY];
+    if (!st->reordered) return;
+    const int64_t c = blockIdx.x;
+    if (threadIdx.x < NKEY) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < CHR; i += BLOCK) {
+        const int64_t r = c * CHR + i;
+        if (r < n) atomicAdd(&cnt[degree_key(rp[r + 1] - rp[r])], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < NKEY) hist[(int64_t)threadIdx.x * nch + c] = cnt[threadIdx.x];
+}
+
+// Stable ranks: new position = (rows of earlier classes) + (rows of this
+// class in earlier chunks) + (rows of this class earlier in this chunk).
+__global__ __launch_bounds__(BLOCK) void k_rl_rank(const State* st, const int64_t* rp, int64_t n, int64_t nch,
+                                                   const uint64_t* off, int32_t* perm, int32_t* iperm) {
+    __shared__ uint64_t run[NKEY];
+    __shared__ uint32_t wcnt[WAVES][NKEY];
+    if (!st->reordered) return;
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x < NKEY) run[threadIdx.x] = off[(int64_t)threadIdx.x * nch + c];
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int base = 0; base < CHR; base += BLOCK) {
+        for (int i = threadIdx.x; i < WAVES * NKEY; i += BLOCK) wcnt[i / NKEY][i % NKEY] = 0u;
+        __syncthreads();
+        const int64_t r = c * CHR + base + threadIdx.x;
+        const bool valid = r < n;
+        const int key = valid ? degree_key(rp[r + 1] - rp[r]) : 0;
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 6; ++bit) {
+            const bool on = (key >> bit) & 1;
+            const uint64_t bb = __ballot(valid && on);
+            same &= on ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(same & below);
+        if (valid && rank == 0) wcnt[w][key] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint64_t pos = run[key] + rank;
+            for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][key];
+            perm[pos] = (int32_t)r;
+            iperm[r] = (int32_t)pos;
+        }
+        __syncthreads();
+        if (threadIdx.x < NKEY) {
+            uint64_t add = 0;
+            for (int ww = 0; ww < WAVES; ++ww) add += wcnt[ww][threadIdx.x];
+            run[threadIdx.x] += add;
+        }
+        __syncthreads();
+    }
+}
+
+// Row lengths of the relabelled matrix into rp2 (scanned afterwards).
+__global__ __launch_bounds__(BLOCK) void k_rl_rowlen(const State* st, const int64_t* rp, int64_t n,
+                                                     const int32_t* perm, int64_t* rp2, int64_t nnz) {
+    if (!st->reordered) return;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const int64_t r = perm[i];
+        rp2[i] = rp[r + 1] - rp[r];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) rp2[n] = nnz;
+}
+
+// Copies every row to its new place, columns relabelled.  One wavefront per
+// SpMV tile of the relabelled matrix (balanced over entries and rows): the
+// tile's row pointers are staged in LDS and each entry finds its row there.
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_rl_fill(const State* st, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                                   int64_t n, int64_t nnz, int64_t n_tiles,
+                                                   const int32_t* __restrict__ ob, const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ iperm, const int64_t* __restrict__ rp2,
+                                                   int32_t* __restrict__ col2, VT* __restrict__ val2) {
+    __shared__ int64_t srp[WAVES][TILE + 2];
+    if (!st->reordered) return;
+    const int lane = threadIdx.x & 63;
+    int64_t* s = srp[threadIdx.x >> 6];
+    const TileRange tr = wave_tiles(n_tiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
+        const int64_t r_lo = ob[t], r_hi = ob[t + 1];
+        const int64_t t0 = t * TILE - r_lo;
+        const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
+        // Rows r_lo .. r_last touch the tile; stage rp2[r_lo .. r_last + 1].
+        const int64_t r_last = min(r_hi, n - 1);
+        const int nrp = (int)(r_last - r_lo + 2);
+        for (int i = lane; i < nrp; i += 64) s[i] = rp2[r_lo + i];
+        wave_sync();
+        for (int k = lane; k < cnt; k += 64) {
+            const int64_t q = t0 + k;
+            // Largest i with s[i] <= q (that row's range holds q).
+            int lo = 0, hi = nrp - 2;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            const int64_t src = rp[perm[r_lo + lo]] + (q - s[lo]);
+            col2[q] = iperm[col[src]];
+            val2[q] = val[src];
+        }
+        wave_sync();
+    }
+}
+
+// Tile table over the solve's matrix: ob[t] = first row owned by tile t,
+// ob[n_tiles] = n; clears the split-row tickets.  Owners are non-decreasing
+// in r, so row r writes the entries of the tiles after its predecessor's
+// owner up to its own.
+__global__ __launch_bounds__(BLOCK) void k_setup_tiles(const State* st, int64_t n, int64_t n_tiles, int32_t* ob,
+                                                       uint32_t* tk) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    for (int64_t t = t0; t < n_tiles; t += stride) tk[t] = 0u;
+    if (t0 == 0) ob[n_tiles] = (int32_t)n;
+    if (st->status != 0) return;
+    const int64_t* rp = st->crp;
+    for (int64_t r = t0; r < n; r += stride) {
+        const int64_t own = row_owner(rp, r, n_tiles);
+        const int64_t prev = r > 0 ? row_owner(rp, r - 1, n_tiles) : -1;
+        for (int64_t t = prev + 1; t <= own; ++t) ob[t] = (int32_t)r;
+    }
+}
+
+hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth, int reorder,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, b.st, p.m, p.K, reorth, reorder, unit_roundoff(p.prec),
+                       seed);
+    const int64_t n = a.n, nnz = a.nnz;
+    const int g = (int)std::min<int64_t>((n + BLOCK - 1) / BLOCK, 8192);
+    const int gv = (int)std::min<int64_t>((std::max(n, nnz) + BLOCK - 1) / BLOCK, 8192);
+    hipLaunchKernelGGL(k_validate, dim3(gv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, n, nnz);
+    hipLaunchKernelGGL(k_reorder_decide, dim3(1), dim3(64), 0, s, b.st, a.rowptr, a.col, a.val, n, nnz, b.rp2,
+                       b.col2, b.val2, b.perm, b.iperm);
+    const int32_t* gate = &b.st->reordered;
+    if (reorder != LZ_REORDER_OFF) {
+        const int64_t nch = (n + CHR - 1) / CHR;
+        hipLaunchKernelGGL(k_rl_hist, dim3((unsigned)nch), dim3(BLOCK), 0, s, b.st, a.rowptr, n, nch, b.scan);
+        scan(gate, b.scan, NKEY * nch, b.bsum, s);
+        hipLaunchKernelGGL(k_rl_rank, dim3((unsigned)nch), dim3(BLOCK), 0, s, b.st, a.rowptr, n, nch, b.scan,
+                           b.perm, b.iperm);
+        hipLaunchKernelGGL(k_rl_rowlen, dim3(g), dim3(BLOCK), 0, s, b.st, a.rowptr, n, b.perm, b.rp2, nnz);
+        scan(gate, (uint64_t*)b.rp2, n, b.bsum, s);
+    }
+    hipLaunchKernelGGL(k_setup_tiles, dim3(g), dim3(BLOCK), 0, s, b.st, n, p.n_tiles, b.ob, b.tk);
+    if (reorder != LZ_REORDER_OFF) {
+        switch (p.prec) {
+            case 0:
+                hipLaunchKernelGGL(k_rl_fill<double>, dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                                   (const double*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
+                                   (double*)b.val2);
+                break;
+            case 1:
+                hipLaunchKernelGGL(k_rl_fill<float>, dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                                   (const float*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
+                                   (float*)b.val2);
+                break;
+            default:
+                hipLaunchKernelGGL(k_rl_fill<uint16_t>, dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                                   (const uint16_t*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
+                                   (uint16_t*)b.val2);
+                break;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lz

@@ -39,6 +39,17 @@ def test_status_strings_and_defaults():
     opt = lz.Options()
     L.lz_options_init(ctypes.byref(opt))
     assert opt.reorth == 2 and opt.report == 1 and opt.seed == 0 and not opt.workspace
+    assert opt.reorder == lz.REORDER["auto"]
+
+
+@pytest.mark.parametrize("field,value", [("reorder", 3), ("reorder", -1), ("reorth", 4)])
+def test_invalid_options_rejected_without_gpu(field, value):
+    L = lz.lib()
+    d = ctypes.c_void_p(16)
+    opt = lz.Options()
+    L.lz_options_init(ctypes.byref(opt))
+    setattr(opt, field, value)
+    assert L.lanczos_topk_ex(d, d, d, 100, 500, 2, 4, 0, None, d, d, ctypes.byref(opt), None) == -1
 
 
 @pytest.mark.parametrize("n,K,m,prec", [(0, 1, 1, 0), (10, 0, 1, 0), (10, 3, 2, 0), (10, 1, 65, 0),

@@ -153,6 +153,64 @@ def test_fp64_solve_on_skewed_rows_matches_oracle(name):
     np.testing.assert_allclose(rep["beta"][1:m], ref["beta"][1:m], rtol=1e-10, atol=1e-12)
 
 
+@pytest.mark.parametrize("reorder", ["off", "hubs"])
+@pytest.mark.parametrize("name", ["rmat14", "rmat14_hubfirst", "mixed6000", "empty_runs_sym"])
+def test_hub_first_relabelling_matches_oracle(name, reorder):
+    # The solve on P A P^T: same Lanczos coefficients (start vector drawn by
+    # original index), eigenvalues, and Ritz vectors back in original order.
+    if name == "empty_runs_sym":
+        rp, c, v = synth.rmat_n(20000, 6.0, seed=21)
+        # isolated vertices between the others: every third row emptied
+        keep = np.arange(rp.size - 1) % 3 != 0
+        rp, c, v = restrict_rows_cols(rp, c, v, keep)
+    else:
+        rp, c, v = SPMV[name]
+    K, m = 6, 20
+    drp, dc, dv = device_csr(rp, c, v, "fp64")
+    vals, vecs, rep = lz.topk(drp, dc, dv, K, m, "fp64", seed=5, reorder=reorder)
+    torch.cuda.synchronize()
+    Y = vecs.cpu().numpy()
+    ref = oracle.topk(rp, c, v, K, m, seed=5)
+    assert rep["reordered"] == (reorder == "hubs")
+    assert rep["restarts"] == ref["restarts"]
+    assert eig_rel_err(vals.cpu().numpy(), ref["vals"]) <= 1e-10
+    np.testing.assert_allclose(rep["alpha"], ref["alpha"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(rep["beta"][1:m], ref["beta"][1:m], rtol=1e-10, atol=1e-12)
+    # Converged pairs: same vector, same sign (largest entry positive).
+    conv = ref["rel_resid"] < 1e-8
+    dots = np.sum(Y * ref["vecs"], axis=0)
+    assert np.all(dots[conv] >= 1 - 1e-8), dots
+    np.testing.assert_allclose(rep["abs_resid"], ref["abs_resid"], rtol=1e-6, atol=1e-12)
+
+
+def restrict_rows_cols(rp, c, v, keep):
+    """Zeroes the rows and columns not in `keep` (the matrix keeps its size)."""
+    n = rp.size - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    ok = keep[rows] & keep[c]
+    cnt = np.bincount(rows[ok], minlength=n)
+    nrp = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    return nrp, c[ok].astype(np.int32), v[ok]
+
+
+@pytest.mark.parametrize("kind", ["rmat", "er"])
+def test_auto_relabelling_decision(kind):
+    # n = 2^17: R-MAT rows are skewed enough to relabel, Erdos-Renyi rows not.
+    n = 1 << 17
+    if kind == "rmat":
+        rp, c, v = synth.rmat(17, 8, seed=4)
+    else:
+        rp, c, v = synth.er(n, 9.0, seed=4)
+    K, m = 4, 16
+    drp, dc, dv = device_csr(rp, c, v, "fp64")
+    vals, vecs, rep = lz.topk(drp, dc, dv, K, m, "fp64", seed=1)
+    torch.cuda.synchronize()
+    assert rep["reordered"] == (kind == "rmat")
+    ref = oracle.topk(rp, c, v, K, m, seed=1)
+    assert eig_rel_err(vals.cpu().numpy(), ref["vals"]) <= 1e-10
+    np.testing.assert_allclose(rep["alpha"], ref["alpha"], rtol=1e-10, atol=1e-12)
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 37, 2047, 2049, 4097])
 def test_ragged_sizes(n):
     rp, c, v = synth.er(n, min(9.0, max(n - 1, 0)), seed=n)
