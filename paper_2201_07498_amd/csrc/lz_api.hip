@@ -24,7 +24,11 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.K = K;
     p.m = m;
     p.prec = prec;
+    // Leading dimension: a multiple of LDPAD, made an odd multiple so that the
+    // same row of successive basis columns does not fall on the same HBM
+    // channel (a power-of-two column stride sends them all to one).
     p.ld = ceil_div(n, LDPAD) * LDPAD;
+    if ((p.ld / LDPAD) % 2 == 0) p.ld += LDPAD;
     p.KB = (int32_t)std::max<int64_t>(8, ceil_div(K, 8) * 8);
     p.g_orth = (int32_t)std::min<int64_t>(OGRID, p.ld / BLOCK);
     p.n_tiles = ceil_div(nnz + n, TILE);
@@ -59,6 +63,7 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_val2 = take((size_t)nnz * vb);
     p.off_perm = take((size_t)n * 4);
     p.off_iperm = take((size_t)n * 4);
+    p.off_gm = take((size_t)NCMAX * NCMAX * 8);
     p.bytes = o;
     return p;
 }
@@ -85,6 +90,7 @@ Bufs resolve(const Plan& p, void* base) {
     b.val2 = c + p.off_val2;
     b.perm = (int32_t*)(c + p.off_perm);
     b.iperm = (int32_t*)(c + p.off_iperm);
+    b.gm = (double*)(c + p.off_gm);
     return b;
 }
 
@@ -184,7 +190,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, o.reorder, s));
         LZ_HIP(launch_init(p, b, s));
         if (o.profile) LZ_HIP(hipEventRecord(pev[1], s));
-        for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, s, iter_events(t)));
+        for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, o.reorth, s, iter_events(t)));
         // Breakdowns consume iterations without advancing j: run more until
         // m steps are done (bounded; each round advances j).
         for (int round = 0; round < 2 * LZ_MAX_STEPS + 2; ++round) {
@@ -192,7 +198,8 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             LZ_HIP(hipStreamSynchronize(s));
             if (hst->status != 0 || hst->j >= m) break;
             const int extra = m - hst->j;
-            for (int t = 0; t < extra; ++t) LZ_HIP(launch_iteration(p, b, a, m, s, iter_events(launched + t)));
+            for (int t = 0; t < extra; ++t)
+                LZ_HIP(launch_iteration(p, b, a, m, o.reorth, s, iter_events(launched + t)));
             launched += extra;
         }
         if (hst->status == 0 && hst->j < m) {

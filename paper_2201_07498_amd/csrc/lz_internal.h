@@ -69,7 +69,7 @@ struct Plan {
     int64_t n_tiles = 0;
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
            off_Y = 0, off_Z = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0, off_tail = 0, off_rp2 = 0,
-           off_col2 = 0, off_val2 = 0, off_perm = 0, off_iperm = 0;
+           off_col2 = 0, off_val2 = 0, off_perm = 0, off_iperm = 0, off_gm = 0;
     size_t bytes = 0;
 };
 
@@ -102,6 +102,7 @@ struct Bufs {
     void* val2;
     int32_t* perm;
     int32_t* iperm;
+    double* gm;        // Gram matrix of the unit stored basis, NCMAX x NCMAX
 };
 Bufs resolve(const Plan& p, void* base);
 
@@ -117,11 +118,12 @@ struct Csr {
 hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth, int reorder,
                         hipStream_t s);
 hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s);
-// One Lanczos iteration (SpMV or restart draw, two CGS passes, store).
+// One Lanczos iteration (SpMV or restart draw, reorthogonalisation, store);
+// `reorth` is the solve's LZ_REORTH_* mode (it selects the kernels).
 // `ncols_bound` >= j+1 for every j the iteration can see.
 // With `ev` non-null, ev[0] is recorded before the SpMV, ev[1] after it and
 // ev[2] after the reorthogonalisation kernels.
-hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols_bound,
+hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols_bound, int reorth,
                             hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
                          double* out_vecs, int report, hipStream_t s);

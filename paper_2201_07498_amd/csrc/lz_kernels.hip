@@ -1,11 +1,16 @@
 // gfx950 kernels of one Lanczos iteration (Sec. II, Algorithm 1) and the
 // start vector.
 //
-// One iteration is four kernels:
+// One iteration is three kernels:
 //   k_spmv_step      w = A v_j - beta_j v_{j-1};  alpha_j = v_j . (A v_j)
-//   k_orth_dot       c  = V^T w                  (first Gram-Schmidt pass)
-//   k_orth_upd_dot   w' = w - V c;  c2 = V^T w'  (update fused with the second dots)
-//   k_orth_upd_store v_{j+1} = w' - V c2 in the basis precision; beta_{j+1}
+//   k_orth_dot       c = V^T w; the second Gram-Schmidt coefficients
+//                    c2 = V^T (w - V c) = c - G c from the Gram matrix G of
+//                    the stored basis (no second pass over V)
+//   k_orth_upd_store v_{j+1} = w - V (c + c2) in the basis precision;
+//                    beta_{j+1}; the new column of G
+// With one pass or none, a restart vector (always orthogonalised twice) takes
+// the classical second pass instead: k_orth_upd_dot, w' = w - V c and
+// c2 = V^T w', runs between the two.
 // Global sums are per-workgroup partials that the last workgroup to finish
 // adds in workgroup order, so results do not depend on scheduling.  The step
 // index and every coefficient stay in device memory.
@@ -26,7 +31,7 @@ namespace lz {
 // (its padding rows must stay zero).
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_init(State* st, typename Tr<P>::V* V, typename Tr<P>::W* w,
-                                                int64_t n, int64_t ld, double* part) {
+                                                int64_t n, int64_t ld, double* part, double* gm) {
     using VT = typename Tr<P>::V;
     using WT = typename Tr<P>::W;
     __shared__ double sh[BLOCK / 64];
@@ -51,6 +56,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(State* st, typename Tr<P>::V* V,
         const double tot = ordered_sum_dev(part, gridDim.x, sh);
         if (threadIdx.x == 0) {
             st->scale[0] = 1.0 / sqrt(tot);
+            gm[0] = tot * st->scale[0] * st->scale[0];
             st->beta[0] = 0.0;
             st->j = 0;
             st->mode = MODE_NORMAL;
@@ -137,14 +143,16 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
 }
 
 // ------------------------------------------------- reorthogonalisation
-// The dot pass runs unless reorthogonalisation is off; the fused update+dot
-// runs for the two-pass modes.  A restart vector is always orthogonalised
-// twice.
+// The dot pass runs unless reorthogonalisation is off.  The two-pass modes
+// keep the Gram matrix of the stored basis and take the second coefficients
+// from it; the one-pass modes run the classical second pass only for a
+// restart vector (always orthogonalised twice).
 __device__ __forceinline__ bool dot_active(const State* st) {
     return st->reorth != 0 || st->mode == MODE_RESTART;
 }
+__device__ __forceinline__ bool gram_mode(const State* st) { return st->reorth >= 2; }
 __device__ __forceinline__ bool upd_dot_active(const State* st) {
-    return st->reorth >= 2 || st->mode == MODE_RESTART;
+    return !gram_mode(st) && st->mode == MODE_RESTART;
 }
 
 // The dense kernels move 16-byte chunks: R consecutive rows of one basis
@@ -270,11 +278,13 @@ __device__ __forceinline__ void reduce_columns(const double* part, int nb, int n
 template <int P, int NC>
 __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                     const typename Tr<P>::W* __restrict__ w, int64_t ld,
-                                                    double* part) {
+                                                    double* part, double* part2, const double* __restrict__ gm) {
     using VT = typename Tr<P>::V;
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
     __shared__ double red[BLOCK / 64][NC];
+    __shared__ double sc[NC];
+    __shared__ double shd[BLOCK / 64];
     __shared__ int s_last;
     const int j = st->j;
     if (st->status != 0 || j >= st->m || !dot_active(st)) return;
@@ -289,10 +299,14 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
     double acc[NCL];
 #pragma unroll
     for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
+    double nrm = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
         const int64_t r0 = base + rowgrp * R;
         double x[R];
         w_load(w + r0, x);
+        if (cs == 0)
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) nrm += x[rr] * x[rr];
         CT ch[NCL];
 #pragma unroll
         for (int kk = 0; kk < NCL; ++kk) {
@@ -313,9 +327,39 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
         }
     }
     publish_split<NC, CS, NCL>(acc, nc, part, red);
+    nrm = block_sum(nrm, shd);
+    if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_DOT], gridDim.x, &s_last)) {
         reduce_columns<NC>(part, gridDim.x, nc, st->scale, st->c, red);
-        if (!upd_dot_active(st)) {       // one pass: the store kernel uses c
+        const double wn = ordered_sum_dev(part2, gridDim.x, shd);
+        if (gram_mode(st)) {
+            // Second coefficients of classical Gram-Schmidt without a second
+            // pass: V^T (w - V c) = c - G c, G the Gram matrix of the unit
+            // stored basis.  The update then subtracts V (c + c2) at once, in
+            // FP64 registers, so no rounded intermediate w' exists.
+            for (int k = threadIdx.x; k < nc; k += BLOCK) sc[k] = st->c[k];
+            __syncthreads();
+            double c2 = 0.0;
+            if ((int)threadIdx.x < nc) {
+                double gc = 0.0;
+                for (int l = 0; l < nc; ++l) gc += gm[threadIdx.x * NCMAX + l] * sc[l];
+                c2 = sc[threadIdx.x] - gc;
+            }
+            // Selective: skip the correction when it is below the rounding of
+            // the stored vector, ||c2|| <= u_s ||w - V c||, with
+            // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c).
+            double sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : 0.0,
+                             (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : 0.0,
+                             (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : 0.0};
+            for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd);
+            const double w1 = fmax(0.0, wn - 2.0 * sel[1] + sel[2]);
+            const bool corr = st->reorth == 2 || st->mode == MODE_RESTART || sel[0] > st->u_s * st->u_s * w1;
+            if ((int)threadIdx.x < nc) st->c2[threadIdx.x] = sc[threadIdx.x] + (corr ? c2 : 0.0);
+            if (threadIdx.x == 0) {
+                st->wnorm2 = w1;
+                st->second = 1;
+            }
+        } else if (!upd_dot_active(st)) {  // one pass: the store kernel uses c
             for (int k = threadIdx.x; k < nc; k += BLOCK) st->c2[k] = st->c[k];
             if (threadIdx.x == 0) st->second = 1;
         }
@@ -428,18 +472,22 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typenam
     }
 }
 
-// v_{j+1} = w' - V c2 (if the second update runs), stored in the basis
+// v_{j+1} = w - V c2 (c2 holds the total coefficients) stored in the basis
 // precision into column j+1; beta_{j+1} = ||stored column||; breakdown check
-// (beta <= tau = 100 u_s max_i(|alpha_i| + beta_i) starts a restart).
-template <int P, int NC>
+// (beta <= tau = 100 u_s max_i(|alpha_i| + beta_i) starts a restart).  In the
+// two-pass modes the same pass takes the dots of the stored column with the
+// basis: the new row and column of the Gram matrix.
+template <int P, int NC, bool GRAM>
 __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr<P>::V* __restrict__ Vb,
                                                           const typename Tr<P>::W* __restrict__ w, int64_t ld,
-                                                          double* part2) {
+                                                          double* part, double* part2, double* gm) {
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
     __shared__ double coef[NC];
+    __shared__ double red[BLOCK / 64][NC];
+    __shared__ double gcol[NC];
     __shared__ double shd[BLOCK / 64];
-    __shared__ int s_last;
+    __shared__ int s_last, s_accept;
     const int j = st->j;
     if (st->status != 0 || j >= st->m) return;
     const int nc = j + 1;
@@ -447,8 +495,11 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
         if (blockIdx.x == 0 && threadIdx.x == 0) st->status = -1;
         return;
     }
-    const bool second = st->second != 0;
-    const int lo = (st->reorth == 0 && st->mode != MODE_RESTART) ? j : 0;
+    // The Gram variant runs in the two-pass modes, where every column takes
+    // part in the update.
+    const bool second = GRAM || st->second != 0;
+    constexpr bool gram = GRAM;
+    const int lo = (!GRAM && st->reorth == 0 && st->mode != MODE_RESTART) ? j : 0;
     for (int k = threadIdx.x; k < NC; k += BLOCK)
         coef[k] = (second && k >= lo && k < nc) ? st->c2[k] * st->scale[k] : 0.0;
     __syncthreads();
@@ -457,6 +508,9 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
     constexpr int64_t RB = (int64_t)(BLOCK / 64) * GPW * R;
     auto* out = Vb + (int64_t)(j + 1) * ld;
     double nrm = 0.0;
+    double acc[NCL];
+#pragma unroll
+    for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
         const int64_t r0 = base + rowgrp * R;
         double x[R];
@@ -471,19 +525,39 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
             double u[R];
             split_update<P, NC>(ch, coef, cs, lo, nc, u);
 #pragma unroll
+            for (int kk = 0; kk < NCL; ++kk) opaque(ch[kk]);
+#pragma unroll
             for (int rr = 0; rr < R; ++rr) x[rr] -= u[rr];
+            v_round_store(out + r0, x, cs == 0);
+            if (gram)
+#pragma unroll
+                for (int kk = 0; kk < NCL; ++kk) {
+                    const int k = cs * NCL + kk;
+                    if (k < nc) {
+                        double v[R];
+                        unpack(ch[kk], v);
+                        double s = 0.0;
+#pragma unroll
+                        for (int rr = 0; rr < R; ++rr) s += v[rr] * x[rr];
+                        acc[kk] += s;
+                    }
+                }
+        } else {
+            v_round_store(out + r0, x, cs == 0);
         }
-        v_round_store(out + r0, x, cs == 0);
         if (cs == 0)
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) nrm += x[rr] * x[rr];
     }
+    if (gram) publish_split<NC, CS, NCL>(acc, nc, part, red);
     nrm = block_sum(nrm, shd);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_STORE], gridDim.x, &s_last)) {
+        if (gram) reduce_columns<NC>(part, gridDim.x, nc, st->scale, gcol, red);
         const double tot = ordered_sum_dev(part2, gridDim.x, shd);
         if (threadIdx.x == 0) {
             const double b = sqrt(tot);
+            int accept = 0;
             if (!isfinite(b)) {
                 st->status = -7;               // LZ_ERR_NONFINITE
                 st->j = st->m;
@@ -501,6 +575,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
                     st->beta[j + 1] = b;
                     st->scale[j + 1] = b > 0.0 ? 1.0 / b : 0.0;
                     st->j = j + 1;
+                    accept = 1;
                 }
             } else {
                 if (!(b > 0.0)) {
@@ -511,8 +586,22 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
                     st->beta[j + 1] = 0.0;
                     st->mode = MODE_NORMAL;
                     st->j = j + 1;
+                    accept = 1;
                 }
             }
+            s_accept = accept;
+        }
+        __syncthreads();
+        if (gram && s_accept) {
+            // Gram entries of the unit stored vectors: column j+1 against 0..j
+            // (gcol already carries scale_k) and its own squared norm.
+            const double sn = st->scale[j + 1];
+            for (int k = threadIdx.x; k < nc; k += BLOCK) {
+                const double g = gcol[k] * sn;
+                gm[k * NCMAX + (j + 1)] = g;
+                gm[(j + 1) * NCMAX + k] = g;
+            }
+            if (threadIdx.x == 0) gm[(j + 1) * NCMAX + (j + 1)] = tot * sn * sn;
         }
     }
 }
@@ -521,7 +610,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
 static inline int nc_bucket(int ncols) { return ((ncols + 7) / 8) * 8; }
 
 template <int P>
-static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int ncols, hipStream_t s,
+static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int ncols, int reorth, hipStream_t s,
                               hipEvent_t* ev) {
     using VT = typename Tr<P>::V;
     using WT = typename Tr<P>::W;
@@ -535,11 +624,16 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
 #define LZ_ORTH_CASE(NCV)                                                                                  \
     case NCV:                                                                                              \
         hipLaunchKernelGGL((k_orth_dot<P, NCV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, w, p.ld,      \
-                           b.part);                                                                        \
-        hipLaunchKernelGGL((k_orth_upd_dot<P, NCV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, w, p.ld,  \
-                           b.part, b.part2);                                                               \
-        hipLaunchKernelGGL((k_orth_upd_store<P, NCV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, w,     \
-                           p.ld, b.part2);                                                                 \
+                           b.part, b.part2, b.gm);                                                         \
+        if (reorth < 2)                                                                                    \
+            hipLaunchKernelGGL((k_orth_upd_dot<P, NCV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, w,    \
+                               p.ld, b.part, b.part2);                                                     \
+        if (reorth >= 2)                                                                                   \
+            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, true>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, \
+                               w, p.ld, b.part, b.part2, b.gm);                                            \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, false>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st,  \
+                               V, w, p.ld, b.part, b.part2, b.gm);                                         \
         break;
     switch (nb) {
         LZ_ORTH_CASE(8)
@@ -558,12 +652,12 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols, hipStream_t s,
+hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols, int reorth, hipStream_t s,
                             hipEvent_t* ev) {
     switch (p.prec) {
-        case 0: return iteration_p<0>(p, b, a, ncols, s, ev);
-        case 1: return iteration_p<1>(p, b, a, ncols, s, ev);
-        case 2: return iteration_p<2>(p, b, a, ncols, s, ev);
+        case 0: return iteration_p<0>(p, b, a, ncols, reorth, s, ev);
+        case 1: return iteration_p<1>(p, b, a, ncols, reorth, s, ev);
+        case 2: return iteration_p<2>(p, b, a, ncols, reorth, s, ev);
     }
     return hipErrorInvalidValue;
 }
@@ -572,15 +666,15 @@ hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s) {
     switch (p.prec) {
         case 0:
             hipLaunchKernelGGL(k_init<0>, dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, (double*)b.V, (double*)b.w, p.n,
-                               p.ld, b.part2);
+                               p.ld, b.part2, b.gm);
             break;
         case 1:
             hipLaunchKernelGGL(k_init<1>, dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, (float*)b.V, (float*)b.w, p.n,
-                               p.ld, b.part2);
+                               p.ld, b.part2, b.gm);
             break;
         case 2:
             hipLaunchKernelGGL(k_init<2>, dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, (uint16_t*)b.V, (float*)b.w,
-                               p.n, p.ld, b.part2);
+                               p.n, p.ld, b.part2, b.gm);
             break;
         default:
             return hipErrorInvalidValue;

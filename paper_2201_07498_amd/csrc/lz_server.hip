@@ -185,7 +185,8 @@ hipError_t Server::launch_lanczos(Slot& s) {
     auto body = [&]() -> hipError_t {
         hipError_t e = launch_setup(p, s.bufs, s.csr, r.seed, r.reorth, LZ_REORDER_AUTO, s.stream);
         if (e == hipSuccess) e = launch_init(p, s.bufs, s.stream);
-        for (int t = 0; t < p.m && e == hipSuccess; ++t) e = launch_iteration(p, s.bufs, s.csr, t + 1, s.stream);
+        for (int t = 0; t < p.m && e == hipSuccess; ++t)
+            e = launch_iteration(p, s.bufs, s.csr, t + 1, r.reorth, s.stream);
         return e;
     };
     if (!use_graphs) return body();
@@ -266,7 +267,8 @@ void Server::advance(Slot& s) {
         if (st->j < p.m) {              // breakdowns consumed iterations: run more
             if (++s.rounds > MAX_RESTART_ROUNDS) return complete(s, LZ_ERR_BREAKDOWN);
             hipError_t e = hipSuccess;
-            for (int t = st->j; t < p.m && e == hipSuccess; ++t) e = launch_iteration(p, s.bufs, s.csr, p.m, s.stream);
+            for (int t = st->j; t < p.m && e == hipSuccess; ++t)
+                e = launch_iteration(p, s.bufs, s.csr, p.m, q->r.reorth, s.stream);
             if (e == hipSuccess) e = hipMemcpyAsync(s.hstate, s.bufs.st, sizeof(State), hipMemcpyDeviceToHost, s.stream);
             if (e == hipSuccess) e = hipEventRecord(s.ev_phase, s.stream);
             if (e != hipSuccess) complete(s, LZ_ERR_HIP);
