@@ -350,6 +350,8 @@ def main():
         "lanczos_steps_per_s": m / (R["t_lanczos_ms"] * 1e-3) if R["t_lanczos_ms"] > 0 else None,
         "resid_max": float(np.max(rep["resid"])),
         "ortho_loss": rep["ortho_loss"],
+        "jacobi_sweeps": rep["jacobi_sweeps"],
+        "relabelled": rep["reordered"],
         "roofline": {"bound": "hbm", "kernel": "k_spmv (Lanczos step SpMV)",
                      "achieved": R["spmv_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": R["spmv_gbps"] / HBM_PEAK_GBPS, "traffic": None,

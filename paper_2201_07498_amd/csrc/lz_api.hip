@@ -47,7 +47,7 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_state = take(sizeof(State));
     p.off_V = take((size_t)p.ld * (size_t)(m + 1) * vb);
     p.off_w = take((size_t)p.ld * wb);
-    p.off_part = take((size_t)std::max(p.g_orth, 256) * 256 * 8);
+    p.off_part = take((size_t)std::max(p.g_orth, 1024) * 256 * 8);
     p.off_part2 = take((size_t)std::max(std::max(p.g_tile, p.g_orth), 2048) * 64 * 8);
     p.off_scan = take((size_t)scan_n * 8);
     p.off_bsum = take((size_t)(ceil_div(scan_n, 2048) + 2) * 8);
@@ -182,7 +182,15 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         }
         const Bufs b = resolve(p, ws);
         const Csr a{csr_rowptr, csr_col, csr_val, n, nnz};
-        hst = new State;
+        // Pinned host copy of the state (one per host thread, kept for the
+        // process): pageable copies are staged in many small blits.
+        static thread_local State* pinned = nullptr;
+        if (!pinned && hipHostMalloc((void**)&pinned, sizeof(State), hipHostMallocDefault) != hipSuccess) {
+            pinned = nullptr;
+            rc = LZ_ERR_OUT_OF_MEMORY;
+            goto done;
+        }
+        hst = pinned;
         if (o.profile) {
             for (int i = 0; i < 4; ++i) LZ_HIP(hipEventCreate(&pev[i]));
             LZ_HIP(hipEventRecord(pev[0], s));
@@ -194,7 +202,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         // Breakdowns consume iterations without advancing j: run more until
         // m steps are done (bounded; each round advances j).
         for (int round = 0; round < 2 * LZ_MAX_STEPS + 2; ++round) {
-            LZ_HIP(hipMemcpyAsync(hst, b.st, sizeof(State), hipMemcpyDeviceToHost, s));
+            LZ_HIP(hipMemcpyAsync(hst, b.st, STATE_HEAD_BYTES, hipMemcpyDeviceToHost, s));
             LZ_HIP(hipStreamSynchronize(s));
             if (hst->status != 0 || hst->j >= m) break;
             const int extra = m - hst->j;
@@ -209,7 +217,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         if (o.profile) LZ_HIP(hipEventRecord(pev[2], s));
         if (hst->status == 0) LZ_HIP(launch_finish(p, b, a, out_vals, out_vecs, o.report, s));
         if (o.profile) LZ_HIP(hipEventRecord(pev[3], s));
-        LZ_HIP(hipMemcpyAsync(hst, b.st, sizeof(State), hipMemcpyDeviceToHost, s));
+        LZ_HIP(hipMemcpyAsync(hst, b.st, STATE_REPORT_BYTES, hipMemcpyDeviceToHost, s));
         LZ_HIP(hipStreamSynchronize(s));
         rc = hst->status;
         if (report) {
@@ -257,7 +265,6 @@ done:
     for (hipEvent_t e : iev) (void)hipEventDestroy(e);
     for (hipEvent_t e : pev)
         if (e) (void)hipEventDestroy(e);
-    delete hst;
     return rc;
 }
 

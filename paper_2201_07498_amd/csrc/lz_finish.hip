@@ -20,7 +20,7 @@ constexpr int JBLOCK = 1024;      // Jacobi workgroup: one round is a single par
 // zeta = (t_qq - t_pp)/(2 t_pq), t = sgn(zeta)/(|zeta| + sqrt(1+zeta^2)),
 // c = 1/sqrt(1+t^2), s = t c.  A rotation is skipped when |t_pq| is
 // negligible (<= eps sqrt|t_pp t_qq| or <= eps^2 ||T||_F); the method stops
-// after a sweep without rotations.
+// at a sweep without rotations (counted, not run).
 //
 // Disjoint rotations commute, so a round is one parallel step: T' = J^T T J
 // is updated as independent 2x2 blocks (rows of pair a, columns of pair b),
@@ -54,6 +54,26 @@ __device__ void jacobi_core(int m, double (*T)[MMAX + 1], double (*S)[MMAX + 1],
     __syncthreads();
     int sweeps = -1;
     for (int sweep = 1; sweep <= JMAX_SWEEPS; ++sweep) {
+        // A sweep rotates nothing exactly when every pair already passes the
+        // skip test at its start (T does not change within such a sweep), so
+        // that sweep is detected here instead of being run.
+        if (threadIdx.x == 0) *rot_flag = 0;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < m * m; idx += nt) {
+            const int p = idx / m, q = idx % m;
+            if (p < q) {
+                const double apq = T[p][q];
+                if (!(fabs(apq) <= eps * sqrt(fabs(T[p][p] * T[q][q])) || fabs(apq) <= eps * eps * fro))
+                    *rot_flag = 1;
+            }
+        }
+        __syncthreads();
+        const int pending = *rot_flag;
+        __syncthreads();
+        if (!pending) {
+            sweeps = sweep;
+            break;
+        }
         if (threadIdx.x == 0) *rot_flag = 0;
         __syncthreads();
         for (int round = 0; round < me - 1; ++round) {
@@ -116,12 +136,6 @@ __device__ void jacobi_core(int m, double (*T)[MMAX + 1], double (*S)[MMAX + 1],
                 S[r][qb] = rs[b] * sp + rc[b] * sq;
             }
             __syncthreads();
-        }
-        const int any = *rot_flag;
-        __syncthreads();
-        if (!any) {
-            sweeps = sweep;
-            break;
         }
     }
     *sweeps_out = sweeps;
@@ -235,8 +249,10 @@ __global__ __launch_bounds__(BLOCK) void k_ritz(const State* st, const typename 
 }
 
 // Per Ritz column k: norm and the entry of largest modulus (lowest original
-// row on ties) -> ysc[k] = sign(that entry) / norm.  Lane k of each group of KB2
-// lanes owns column k.
+// row on ties) -> ysc[k] = sign(that entry) / norm.  Lane k of each group of
+// KB2 lanes owns column k.  NOROW marks "no row yet" (exact as a double and
+// as an int64).
+constexpr int64_t NOROW = int64_t(1) << 62;
 __global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __restrict__ Y, int64_t n, int KB2,
                                                     double* part) {
     __shared__ double s_n[BLOCK], s_a[BLOCK], s_v[BLOCK];
@@ -246,21 +262,32 @@ __global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __r
     const int K = st->K, G = gridDim.x;
     const int groups = BLOCK / KB2, g = threadIdx.x / KB2, k = threadIdx.x % KB2;
     double nrm = 0.0, best = -1.0, bval = 0.0;
-    int64_t bidx = INT64_MAX;
+    int64_t bidx = NOROW;
     const int32_t* perm = st->perm;
-    if (k < K)
-        for (int64_t r = (int64_t)blockIdx.x * groups + g; r < n; r += (int64_t)G * groups) {
-            const double v = Y[r * K + k];
-            nrm += v * v;
-            const double a = fabs(v);
-            const int64_t ro = perm ? perm[r] : r;
-            if (a > best || (a == best && ro < bidx)) { best = a; bval = v; bidx = ro; }
+    auto visit = [&](int64_t r, double v) {
+        nrm += v * v;
+        const double a = fabs(v);
+        const int64_t ro = perm ? perm[r] : r;
+        if (a > best || (a == best && ro < bidx)) { best = a; bval = v; bidx = ro; }
+    };
+    if (k < K) {
+        const int64_t S = (int64_t)G * groups;
+        int64_t r = (int64_t)blockIdx.x * groups + g;
+        for (; r + 3 * S < n; r += 4 * S) {       // four rows in flight
+            const double v0 = Y[r * K + k], v1 = Y[(r + S) * K + k], v2 = Y[(r + 2 * S) * K + k],
+                         v3 = Y[(r + 3 * S) * K + k];
+            visit(r, v0);
+            visit(r + S, v1);
+            visit(r + 2 * S, v2);
+            visit(r + 3 * S, v3);
         }
+        for (; r < n; r += S) visit(r, Y[r * K + k]);
+    }
     s_n[threadIdx.x] = nrm; s_a[threadIdx.x] = best; s_v[threadIdx.x] = bval; s_i[threadIdx.x] = bidx;
     __syncthreads();
     if ((int)threadIdx.x < K) {
         double tn = 0.0, ta = -1.0, tv = 0.0;
-        int64_t ti = INT64_MAX;
+        int64_t ti = NOROW;
         for (int gg = 0; gg < groups; ++gg) {
             const int t = gg * KB2 + threadIdx.x;
             tn += s_n[t];
@@ -273,26 +300,39 @@ __global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __r
         st_dev(pb + 3, (double)ti);
     }
     if (last_block(&st->ticket[TK_RITZ], (uint32_t)G, &s_last)) {
-        const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
-        double tn = 0.0, ta = -1.0, tv = 0.0, ti = 1e300;
-        if (l < K)
-            for (int b = q; b < G; b += 4) {
-                const double* pb = part + ((int64_t)b * 64 + l) * 4;
-                tn += ld_dev(pb);
-                const double a = ld_dev(pb + 1), i = ld_dev(pb + 3);
-                if (a > ta || (a == ta && i < ti)) { ta = a; tv = ld_dev(pb + 2); ti = i; }
+        // Thread (g, k) folds workgroups g, g + groups, ... of column k (four
+        // loads in flight), then the groups are folded in order.
+        double tn = 0.0, ta = -1.0, tv = 0.0, ti = (double)NOROW;
+        auto fold = [&](const double* pb) {
+            const double nn = ld_dev(pb), a = ld_dev(pb + 1), v = ld_dev(pb + 2), i = ld_dev(pb + 3);
+            tn += nn;
+            if (a > ta || (a == ta && i < ti)) { ta = a; tv = v; ti = i; }
+        };
+        if (k < K) {
+            int b = g;
+            for (; b + 3 * groups < G; b += 4 * groups) {
+                const double* p0 = part + ((int64_t)b * 64 + k) * 4;
+                const double* p1 = part + ((int64_t)(b + groups) * 64 + k) * 4;
+                const double* p2 = part + ((int64_t)(b + 2 * groups) * 64 + k) * 4;
+                const double* p3 = part + ((int64_t)(b + 3 * groups) * 64 + k) * 4;
+                fold(p0);
+                fold(p1);
+                fold(p2);
+                fold(p3);
             }
+            for (; b < G; b += groups) fold(part + ((int64_t)b * 64 + k) * 4);
+        }
         s_n[threadIdx.x] = tn; s_a[threadIdx.x] = ta; s_v[threadIdx.x] = tv; s_i[threadIdx.x] = (int64_t)ti;
         __syncthreads();
-        if (q == 0 && l < K) {
+        if ((int)threadIdx.x < K) {
             double n2 = 0.0, a2 = -1.0, v2 = 0.0;
-            int64_t i2 = INT64_MAX;
-            for (int qq = 0; qq < 4; ++qq) {
-                const int t = qq * 64 + l;
+            int64_t i2 = NOROW;
+            for (int gg = 0; gg < groups; ++gg) {
+                const int t = gg * KB2 + threadIdx.x;
                 n2 += s_n[t];
                 if (s_a[t] > a2 || (s_a[t] == a2 && s_i[t] < i2)) { a2 = s_a[t]; v2 = s_v[t]; i2 = s_i[t]; }
             }
-            st->ysc[l] = (v2 < 0.0 ? -1.0 : 1.0) / sqrt(n2);
+            st->ysc[threadIdx.x] = (v2 < 0.0 ? -1.0 : 1.0) / sqrt(n2);
         }
     }
 }
@@ -421,38 +461,82 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
     }
 }
 
-// Unit Ritz vectors y_k = ysc_k Y[:,k] into the caller's column-major output
-// in original row order (a 64-row block is gathered row-wise and written
-// column-wise through LDS) and, with the report, the residuals
-// ||A y_k - theta_k y_k|| = ||ysc_k Z[:,k] - theta_k y_k||, summed per pair
-// in a fixed order.
-__global__ __launch_bounds__(BLOCK) void k_resid_out(State* st, const double* __restrict__ Y,
-                                                     const double* __restrict__ Z, int64_t n, int KB2, int report,
-                                                     double* part, double* __restrict__ out) {
-    __shared__ double ys[64][65];
+// Residuals ||A y_k - theta_k y_k|| = ||ysc_k Z[:,k] - theta_k ysc_k Y[:,k]||
+// (Sec. IV-D), streaming Y and Z in the solve's row order; thread (g, k)
+// sums rows g, g + groups, ... of pair k (four rows in flight), workgroup
+// partials are added in a fixed order by the last workgroup.
+__global__ __launch_bounds__(BLOCK) void k_resid(State* st, const double* __restrict__ Y,
+                                                 const double* __restrict__ Z, int64_t n, int KB2, double* part) {
     __shared__ double shz[BLOCK];
     __shared__ double red[4][64];
     __shared__ int s_last;
     if (st->status != 0) return;
     const int K = st->K;
-    const int tid = threadIdx.x, k = tid % KB2;
+    const int tid = threadIdx.x, groups = BLOCK / KB2, g = tid / KB2, k = tid % KB2;
     const bool act = k < K;
     const double ysc = act ? st->ysc[k] : 0.0;
     const double th = act ? st->theta[st->sel[k]] : 0.0;
-    const int32_t* iperm = st->iperm;
     double racc = 0.0;
+    if (act) {
+        auto term = [&](int64_t r) {
+            const double y = ysc * Y[r * K + k];
+            const double d = ysc * Z[r * K + k] - th * y;
+            return d * d;
+        };
+        const int64_t S = (int64_t)gridDim.x * groups;
+        int64_t r = (int64_t)blockIdx.x * groups + g;
+        for (; r + 3 * S < n; r += 4 * S) {
+            const double d0 = term(r), d1 = term(r + S), d2 = term(r + 2 * S), d3 = term(r + 3 * S);
+            racc += d0;
+            racc += d1;
+            racc += d2;
+            racc += d3;
+        }
+        for (; r < n; r += S) racc += term(r);
+    }
+    shz[tid] = racc;
+    __syncthreads();
+    if (tid < KB2) {
+        double sum = 0.0;
+        for (int gg = 0; gg < groups; ++gg) sum += shz[gg * KB2 + tid];
+        st_dev(&part[(int64_t)blockIdx.x * 64 + tid], sum);
+    }
+    if (last_block(&st->ticket[TK_RESID], gridDim.x, &s_last)) {
+        const int q = tid >> 6, l = tid & 63;
+        double sum = 0.0;
+        if (l < K)
+            for (int b = q; b < (int)gridDim.x; b += 4) sum += ld_dev(&part[(int64_t)b * 64 + l]);
+        red[q][l] = sum;
+        __syncthreads();
+        if (q == 0 && l < K) {
+            const double a2 = sqrt((red[0][l] + red[1][l]) + (red[2][l] + red[3][l]));
+            const double tl = st->theta[st->sel[l]];
+            st->abs_resid[l] = a2;
+            st->resid[l] = tl != 0.0 ? a2 / fabs(tl) : a2;
+        }
+    }
+}
+
+// Unit Ritz vectors y_k = ysc_k Y[:,k] into the caller's column-major output
+// in original row order: a 64-row block is gathered row-wise (through the
+// original-to-solve row map when the matrix was relabelled) and written
+// column-wise through LDS.
+__global__ __launch_bounds__(BLOCK) void k_out(const State* st, const double* __restrict__ Y, int64_t n, int KB2,
+                                               double* __restrict__ out) {
+    __shared__ double ys[64][65];
+    if (st->status != 0) return;
+    const int K = st->K;
+    const int tid = threadIdx.x, k = tid % KB2;
+    const bool act = k < K;
+    const double ysc = act ? st->ysc[k] : 0.0;
+    const int32_t* iperm = st->iperm;
     for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < n; r0 += (int64_t)gridDim.x * 64) {
         for (int idx = tid; idx < 64 * KB2; idx += BLOCK) {
             const int row = idx / KB2;
             const int64_t r = r0 + row;
             if (r < n && act) {
                 const int64_t i = iperm ? iperm[r] : r;
-                const double y = ysc * Y[i * K + k];
-                ys[row][k] = y;
-                if (report) {
-                    const double d = ysc * Z[i * K + k] - th * y;
-                    racc += d * d;
-                }
+                ys[row][k] = ysc * Y[i * K + k];
             }
         }
         __syncthreads();
@@ -463,121 +547,106 @@ __global__ __launch_bounds__(BLOCK) void k_resid_out(State* st, const double* __
         }
         __syncthreads();
     }
-    if (!report) return;
-    shz[tid] = racc;
-    __syncthreads();
-    if (tid < KB2) {
-        double s = 0.0;
-        for (int gg = 0; gg < BLOCK / KB2; ++gg) s += shz[gg * KB2 + tid];
-        st_dev(&part[(int64_t)blockIdx.x * 64 + tid], s);
-    }
-    if (last_block(&st->ticket[TK_RESID], gridDim.x, &s_last)) {
-        const int q = tid >> 6, l = tid & 63;
-        double s = 0.0;
-        if (l < K)
-            for (int b = q; b < (int)gridDim.x; b += 4) s += ld_dev(&part[(int64_t)b * 64 + l]);
-        red[q][l] = s;
-        __syncthreads();
-        if (q == 0 && l < K) {
-            const double a = sqrt((red[0][l] + red[1][l]) + (red[2][l] + red[3][l]));
-            const double tl = st->theta[st->sel[l]];
-            st->abs_resid[l] = a;
-            st->resid[l] = tl != 0.0 ? a / fabs(tl) : a;
-        }
-    }
 }
 
 // -------------------------------------------------------- orthogonality
 // Gram matrix G = X^T X of c <= 64 columns (column k scaled by scale[k]) on
-// the FP64 matrix cores.  Every wavefront walks its own 16-row tiles: for
-// each group of 4 rows it loads one operand per 16-column block (lane l holds
-// X[r0 + l/16][16 b + l%16]) and issues v_mfma_f64_16x16x4f64 for every
-// upper block pair (A = 16 columns x 4 rows, B = 4 rows x 16 columns).  The
-// four wavefronts of a workgroup add their blocks in LDS in wave order; the
-// workgroup's upper blocks go to gpart[b][64][64].
+// the FP64 matrix cores.  A workgroup stages panels of 64 rows x c columns in
+// LDS (each column's 64 rows are one coalesced load), then every wavefront
+// multiplies its own upper 16x16 block pairs with v_mfma_f64_16x16x4f64 over
+// the panel's 16 groups of 4 rows (A = 16 columns x 4 rows, B = 4 rows x 16
+// columns; lane l holds P[4g + l/16][16b + l%16]).  Each workgroup writes its
+// upper blocks to gpart[b][64][64].
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int GRT = 16;     // rows per wavefront tile
+constexpr int GPR = 64;     // rows per LDS panel
 
 template <class T, bool ROWMAJOR>
 __global__ __launch_bounds__(BLOCK) void k_gram(const State* st, const T* __restrict__ X, int64_t ldx, int64_t n,
                                                 int which, double* __restrict__ gpart) {
-    __shared__ double L[64][64];
+    __shared__ double P[GPR][64 + 1];
     if (st->status != 0) return;
     const int c = which == 0 ? min(st->j, st->m) : st->K;
     const double* scale = which == 0 ? st->scale : st->ysc;
     const int nb = (c + 15) >> 4;
+    const int npair = nb * (nb + 1) / 2;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int cl = lane & 15, rl = lane >> 4;
-    double sc[4];
-    for (int b = 0; b < 4; ++b) {
-        const int cc = b * 16 + cl;
-        sc[b] = (b < nb && cc < c) ? scale[cc] : 0.0;
-    }
-    d4 acc[10];
-#pragma unroll
-    for (int t = 0; t < 10; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    const int64_t ntiles = (n + GRT - 1) / GRT;
-    const int64_t gw = (int64_t)blockIdx.x * (BLOCK / 64) + wv, nw = (int64_t)gridDim.x * (BLOCK / 64);
-    for (int64_t tile = gw; tile < ntiles; tile += nw) {
-        double x[4][4];      // [row group][column block]
-#pragma unroll
-        for (int k4 = 0; k4 < 4; ++k4) {
-            const int64_t r = tile * GRT + k4 * 4 + rl;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int cc = b * 16 + cl;
-                double v = 0.0;
-                if (b < nb && r < n && cc < c) v = to_d(ROWMAJOR ? X[r * ldx + cc] : X[(int64_t)cc * ldx + r]);
-                x[k4][b] = v * sc[b];
+    // Block pairs (bi <= bj) of this wavefront: pair t for t = wv, wv + 4, ...
+    int pbi[3], pbj[3];
+    int np = 0;
+    for (int bi = 0, t = 0; bi < nb; ++bi)
+        for (int bj = bi; bj < nb; ++bj, ++t)
+            if (t % (BLOCK / 64) == wv && np < 3) {
+                pbi[np] = bi;
+                pbj[np] = bj;
+                ++np;
             }
-        }
+    d4 acc[3];
 #pragma unroll
-        for (int k4 = 0; k4 < 4; ++k4) {
-            int t = 0;
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = bi; bj < 4; ++bj, ++t)
-                    if (bj < nb) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[k4][bi], x[k4][bj], acc[t], 0, 0, 0);
-        }
-    }
-    // Sum the four wavefronts' blocks in LDS (wave order), then publish.
-    for (int w = 0; w < BLOCK / 64; ++w) {
-        if (wv == w) {
-            int t = 0;
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = bi; bj < 4; ++bj, ++t)
-                    if (bj < nb)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            // Accumulator element e of lane l holds D[4e + l/16][l % 16].
-                            const int i = bi * 16 + e * 4 + rl, jj = bj * 16 + cl;
-                            L[i][jj] = (w == 0 ? 0.0 : L[i][jj]) + acc[t][e];
-                        }
+    for (int t = 0; t < 3; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t npanel = (n + GPR - 1) / GPR;
+    for (int64_t pn = blockIdx.x; pn < npanel; pn += gridDim.x) {
+        const int64_t r0 = pn * GPR;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < GPR * 64; idx += BLOCK) {
+            int row, col;
+            if (ROWMAJOR) {
+                row = idx >> 6;
+                col = idx & 63;
+            } else {
+                col = idx / GPR;
+                row = idx % GPR;
+            }
+            const int64_t r = r0 + row;
+            double v = 0.0;
+            if (col < c && r < n) v = to_d(ROWMAJOR ? X[r * ldx + col] : X[(int64_t)col * ldx + r]) * scale[col];
+            P[row][col] = v;
         }
         __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (t < np) {
+                const int bi = pbi[t], bj = pbj[t];
+#pragma unroll 4
+                for (int g = 0; g < GPR / 4; ++g) {
+                    const double a = P[g * 4 + rl][bi * 16 + cl];
+                    const double b = P[g * 4 + rl][bj * 16 + cl];
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
     }
-    double* g = gpart + (int64_t)blockIdx.x * 64 * 64;
-    for (int idx = threadIdx.x; idx < 64 * 64; idx += BLOCK) {
-        const int i = idx / 64, jj = idx % 64;
-        if ((i >> 4) <= (jj >> 4) && (jj >> 4) < nb) g[idx] = L[i][jj];
-    }
+    double* gp = gpart + (int64_t)blockIdx.x * 64 * 64;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t < np)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // Accumulator element e of lane l holds D[4e + l/16][l % 16].
+                const int i = pbi[t] * 16 + e * 4 + rl, jj = pbj[t] * 16 + cl;
+                gp[i * 64 + jj] = acc[t][e];
+            }
+    (void)npair;
 }
 
-// G[i][j] = sum over workgroups of the upper blocks, symmetrised.
+// G[i][j] = sum over workgroups of the upper blocks, symmetrised: one
+// wavefront per entry, lane-strided over the workgroups, then the butterfly
+// (a fixed order).
 __global__ __launch_bounds__(BLOCK) void k_gram_reduce(const State* st, const double* gpart, int nparts, int which,
                                                        double* G) {
     const int c = which == 0 ? min(st->j, st->m) : st->K;
-    const int idx = blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= 64 * 64) return;
-    const int i = idx / 64, jj = idx % 64;
-    if (i >= c || jj >= c) return;
-    const int lo = min(i, jj), hi = max(i, jj);
+    const int lane = threadIdx.x & 63;
+    const int entry = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    if (entry >= 64 * 64) return;
+    const int i = entry / 64, jj = entry % 64;
+    if (i >= c || jj >= c || i > jj) return;
     double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += gpart[(int64_t)b * 4096 + lo * 64 + hi];
-    G[i * 64 + jj] = s;
+    for (int b = lane; b < nparts; b += 64) s += gpart[(int64_t)b * 4096 + i * 64 + jj];
+    s = wave_sum(s);
+    if (lane == 0) {
+        G[i * 64 + jj] = s;
+        G[jj * 64 + i] = s;
+    }
 }
 
 // max |G - I| and, for the Ritz vectors, the mean angle between pairs.
@@ -618,7 +687,7 @@ static int pow2_at_least(int k) {
 }
 
 static int gram_grid(int64_t n) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_PARTS, (n + 4 * GRT - 1) / (4 * GRT)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_PARTS, (n + GPR - 1) / GPR));
 }
 
 template <int P>
@@ -645,22 +714,22 @@ static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* o
             return hipErrorInvalidValue;
     }
     const int kb2 = pow2_at_least(p.K);
-    const int gc = (int)std::max<int64_t>(1, std::min<int64_t>(256, (p.n * kb2 + BLOCK - 1) / BLOCK));
+    const int gc = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p.n * kb2 + 4 * BLOCK - 1) / (4 * BLOCK)));
     hipLaunchKernelGGL(k_colstats, dim3(gc), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, b.part);
     if (report)
         hipLaunchKernelGGL((k_spmm<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, b.Y, b.Z, p.n, p.nnz, p.n_tiles,
                            b.ob, b.tk, b.head, b.tail, kb2);
     const int go = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (p.n + 63) / 64));
-    hipLaunchKernelGGL(k_resid_out, dim3(go), dim3(BLOCK), 0, s, b.st, b.Y, b.Z, p.n, kb2, report, b.part2,
-                       out_vecs);
+    hipLaunchKernelGGL(k_out, dim3(go), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, out_vecs);
     if (!report) return hipGetLastError();
+    hipLaunchKernelGGL(k_resid, dim3(gc), dim3(BLOCK), 0, s, b.st, b.Y, b.Z, p.n, kb2, b.part2);
     const int gg = gram_grid(p.n);
     double* G = b.gram + (int64_t)GRAM_PARTS * 4096;
     hipLaunchKernelGGL((k_gram<VT, false>), dim3(gg), dim3(BLOCK), 0, s, b.st, V, p.ld, p.n, 0, b.gram);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(16), dim3(BLOCK), 0, s, b.st, b.gram, gg, 0, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(64 * 64 / (BLOCK / 64)), dim3(BLOCK), 0, s, b.st, b.gram, gg, 0, G);
     hipLaunchKernelGGL(k_gram_metrics, dim3(1), dim3(BLOCK), 0, s, b.st, G, 0);
     hipLaunchKernelGGL((k_gram<double, true>), dim3(gg), dim3(BLOCK), 0, s, b.st, b.Y, (int64_t)p.K, p.n, 1, b.gram);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(16), dim3(BLOCK), 0, s, b.st, b.gram, gg, 1, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(64 * 64 / (BLOCK / 64)), dim3(BLOCK), 0, s, b.st, b.gram, gg, 1, G);
     hipLaunchKernelGGL(k_gram_metrics, dim3(1), dim3(BLOCK), 0, s, b.st, G, 1);
     return hipGetLastError();
 }
@@ -695,7 +764,7 @@ hipError_t launch_gram_only(int prec, const void* X, int64_t ldx, int64_t n, Sta
         default:
             return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_gram_reduce, dim3(16), dim3(BLOCK), 0, s, st, gram, gg, 0, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(64 * 64 / (BLOCK / 64)), dim3(BLOCK), 0, s, st, gram, gg, 0, G);
     hipLaunchKernelGGL(k_gram_metrics, dim3(1), dim3(BLOCK), 0, s, st, G, 0);
     return hipGetLastError();
 }

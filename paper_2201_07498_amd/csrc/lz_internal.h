@@ -17,7 +17,7 @@ constexpr int TILE = 1024;     // non-zeros per SpMV tile (one wavefront, 16 per
 constexpr int LDPAD = 2048;    // basis leading dimension is a multiple of this
 constexpr int OGRID = 1024;    // orthogonalisation grid cap (workgroups)
 constexpr int SGRID = 2048;    // SpMV grid cap (workgroups)
-constexpr int GRAM_PARTS = 256; // Gram kernel grid cap (per-workgroup 64x64 partials)
+constexpr int GRAM_PARTS = 1024; // Gram kernel grid cap (per-workgroup 64x64 partials)
 
 enum Mode { MODE_NORMAL = 0, MODE_RESTART = 1 };
 
@@ -61,6 +61,12 @@ struct State {
     double S[MMAX * MMAX];     // Jacobi eigenvectors, row-major m x m (stride MMAX)
 };
 
+// Host copies of the state: the header (step, mode, restarts, status) for
+// the restart check, everything but the Jacobi eigenvectors for the report.
+constexpr size_t STATE_HEAD_BYTES = 64;
+constexpr size_t STATE_REPORT_BYTES = offsetof(State, S);
+static_assert(offsetof(State, status) + sizeof(int32_t) <= STATE_HEAD_BYTES, "state header");
+
 // Workspace layout of one solve.  All offsets are in bytes from the base.
 struct Plan {
     int64_t n = 0, nnz = 0, ld = 0;
@@ -86,7 +92,7 @@ struct Bufs {
     State* st;
     void* V;
     void* w;
-    double* part;      // per-workgroup partials: max(g_orth, 256) * 256 doubles
+    double* part;      // per-workgroup partials: max(g_orth, 1024) * 256 doubles
     double* part2;     // second partial buffer (SpMV alpha, residual)
     uint64_t* scan;    // scan scratch (degree-class histogram)
     uint64_t* bsum;    // scan block sums

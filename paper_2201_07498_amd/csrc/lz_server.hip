@@ -219,7 +219,7 @@ bool Server::admit(Slot& s, Req* q) {
     if (e == hipSuccess && r.nnz > 0) e = hipMemcpyAsync(base + l.col, r.col, (size_t)r.nnz * 4, hipMemcpyHostToDevice, s.stream);
     if (e == hipSuccess && r.nnz > 0) e = hipMemcpyAsync(base + l.val, r.val, (size_t)r.nnz * vb, hipMemcpyHostToDevice, s.stream);
     if (e == hipSuccess) e = launch_lanczos(s);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.hstate, s.bufs.st, sizeof(State), hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.hstate, s.bufs.st, STATE_REPORT_BYTES, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipEventRecord(s.ev_phase, s.stream);
     s.phase = LANCZOS;
     return e == hipSuccess;
@@ -269,7 +269,7 @@ void Server::advance(Slot& s) {
             hipError_t e = hipSuccess;
             for (int t = st->j; t < p.m && e == hipSuccess; ++t)
                 e = launch_iteration(p, s.bufs, s.csr, p.m, q->r.reorth, s.stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(s.hstate, s.bufs.st, sizeof(State), hipMemcpyDeviceToHost, s.stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(s.hstate, s.bufs.st, STATE_REPORT_BYTES, hipMemcpyDeviceToHost, s.stream);
             if (e == hipSuccess) e = hipEventRecord(s.ev_phase, s.stream);
             if (e != hipSuccess) complete(s, LZ_ERR_HIP);
             return;
@@ -278,7 +278,7 @@ void Server::advance(Slot& s) {
         if (e == hipSuccess) e = hipMemcpyAsync(s.hvals, s.dvals, sizeof(double) * p.K, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess && q->r.out_vecs)
             e = hipMemcpyAsync(q->r.out_vecs, s.dvecs, sizeof(double) * p.n * p.K, hipMemcpyDeviceToHost, s.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.hstate, s.bufs.st, sizeof(State), hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.hstate, s.bufs.st, STATE_REPORT_BYTES, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.ev_phase, s.stream);
         if (e != hipSuccess) return complete(s, LZ_ERR_HIP);
         s.phase = FINISH;

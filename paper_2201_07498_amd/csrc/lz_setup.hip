@@ -61,13 +61,21 @@ __global__ __launch_bounds__(BLOCK) void k_validate(State* st, const int64_t* rp
     }
     for (int64_t p = t0; p < nnz; p += stride) bad |= (col[p] < 0) || ((int64_t)col[p] >= n);
     if (bad) __hip_atomic_store(&st->status, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // One atomic per workgroup (the grid is capped, so contention is small).
+    __shared__ uint64_t smx[BLOCK / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const uint64_t v = __shfl_xor(mx, o, 64);
         mx = v > mx ? v : mx;
     }
-    if ((threadIdx.x & 63) == 0 && mx > 0)
-        __hip_atomic_fetch_max(&st->maxdeg, (unsigned long long)mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((threadIdx.x & 63) == 0) smx[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < BLOCK / 64; ++i) mx = smx[i] > mx ? smx[i] : mx;
+        if (mx > 0)
+            __hip_atomic_fetch_max(&st->maxdeg, (unsigned long long)mx, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Chooses the matrix of the solve and publishes its pointers in the state.
@@ -315,7 +323,7 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
                        seed);
     const int64_t n = a.n, nnz = a.nnz;
     const int g = (int)std::min<int64_t>((n + BLOCK - 1) / BLOCK, 8192);
-    const int gv = (int)std::min<int64_t>((std::max(n, nnz) + BLOCK - 1) / BLOCK, 8192);
+    const int gv = (int)std::min<int64_t>((std::max(n, nnz) + BLOCK - 1) / BLOCK, 1024);
     hipLaunchKernelGGL(k_validate, dim3(gv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, n, nnz);
     hipLaunchKernelGGL(k_reorder_decide, dim3(1), dim3(64), 0, s, b.st, a.rowptr, a.col, a.val, n, nnz, b.rp2,
                        b.col2, b.val2, b.perm, b.iperm);
