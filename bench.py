@@ -295,6 +295,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t = time.perf_counter()
+    print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
     W = workload(args.workload)
     if args.precisions:
         W["precisions"] = tuple(args.precisions.split(","))

@@ -96,7 +96,10 @@ typedef struct lz_options {
 typedef struct lz_report {
     int32_t status;          /* lz_status of the solve */
     int32_t m_eff;           /* Lanczos steps taken (= m on success) */
-    int32_t restarts;        /* breakdowns met (beta <= tau) */
+    int32_t restarts;        /* breakdowns met: beta_{i+1} <= 100 u_w
+                                max_j(|alpha_j| + beta_j), u_w the unit
+                                roundoff of the working vector (2^-53 in
+                                FP64 mode, 2^-24 in the FP32/BF16 modes) */
     int32_t jacobi_sweeps;
     double beta_last;        /* beta_{m+1}: norm of the final residual vector */
     double resid[LZ_MAX_STEPS];      /* ||A y_k - theta_k y_k|| / |theta_k|

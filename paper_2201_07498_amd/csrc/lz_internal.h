@@ -37,7 +37,8 @@ struct State {
     int32_t n_items, n_long, sweeps, pad0;
     uint32_t ticket[TK_COUNT];
     uint64_t seed;
-    double u_s;           // unit roundoff of the stored basis
+    double u_s;           // unit roundoff of the stored basis (selective reorthogonalisation)
+    double u_w;           // unit roundoff of the working vector and SpMV accumulation (breakdown)
     double tnorm;         // max_j (|alpha_j| + beta_j), scales the breakdown threshold
     double wnorm2;        // ||w'||^2 after the first update (selective second pass)
     // Matrix of the solve: the caller's CSR or its hub-first relabelling.
@@ -84,6 +85,9 @@ inline size_t work_bytes(int prec) { return prec == 0 ? 8 : 4; }
 inline double unit_roundoff(int prec) {
     return prec == 0 ? 1.1102230246251565e-16 : (prec == 1 ? 5.9604644775390625e-08 : 3.90625e-03);
 }
+// The working vector and the SpMV accumulator are FP64 in FP64 mode and FP32
+// in both mixed modes.
+inline double work_roundoff(int prec) { return prec == 0 ? 1.1102230246251565e-16 : 5.9604644775390625e-08; }
 
 Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec);
 

@@ -474,7 +474,8 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typenam
 
 // v_{j+1} = w - V c2 (c2 holds the total coefficients) stored in the basis
 // precision into column j+1; beta_{j+1} = ||stored column||; breakdown check
-// (beta <= tau = 100 u_s max_i(|alpha_i| + beta_i) starts a restart).  In the
+// (beta <= tau = 100 u_w max_i(|alpha_i| + beta_i), u_w the unit roundoff of
+// the working vector, starts a restart).  In the
 // two-pass modes the same pass takes the dots of the stored column with the
 // basis: the new row and column of the Gram matrix.
 template <int P, int NC, bool GRAM>
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
             } else if (st->mode == MODE_NORMAL) {
                 const double t = fabs(st->alpha[j]) + st->beta[j];
                 if (t > st->tnorm) st->tnorm = t;
-                const double tau = 100.0 * st->u_s * st->tnorm;
+                const double tau = 100.0 * st->u_w * st->tnorm;
                 if (!(b > tau) && j + 1 < st->m) {
                     // Breakdown: the Krylov space is invariant.  T gets a zero
                     // coupling and the next iteration draws a restart vector.

@@ -29,7 +29,7 @@ constexpr double REORDER_SKEW = 32.0;
 constexpr int CHR = 4096;          // rows per counting-sort chunk (one workgroup)
 constexpr int NKEY = 64;           // degree classes
 
-__global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double u_s, uint64_t seed) {
+__global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double u_s, double u_w, uint64_t seed) {
     uint64_t* p = reinterpret_cast<uint64_t*>(st);
     const size_t words = sizeof(State) / 8;
     for (size_t i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0ull;
@@ -40,6 +40,7 @@ __global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double
         st->reorth = reorth;
         st->reorder = reorder;
         st->u_s = u_s;
+        st->u_w = u_w;
         st->seed = seed;
     }
 }
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(BLOCK) void k_setup_tiles(const State* st, int64_t 
 hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth, int reorder,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, b.st, p.m, p.K, reorth, reorder, unit_roundoff(p.prec),
-                       seed);
+                       work_roundoff(p.prec), seed);
     const int64_t n = a.n, nnz = a.nnz;
     const int g = (int)std::min<int64_t>((n + BLOCK - 1) / BLOCK, 8192);
     const int gv = (int)std::min<int64_t>((std::max(n, nnz) + BLOCK - 1) / BLOCK, 1024);
