@@ -135,6 +135,8 @@ hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s);
 // ev[2] after the reorthogonalisation kernels.
 hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols_bound, int reorth,
                             hipStream_t s, hipEvent_t* ev = nullptr);
+// The Lanczos-step SpMV of the current iteration (or its restart draw).
+void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s);
 hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
                          double* out_vecs, int report, hipStream_t s);
 hipError_t launch_spmv_plain(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y,

@@ -1,0 +1,124 @@
+// The Lanczos-step SpMV and the standalone SpMV on gfx950 (Algorithm 1, the
+// SpMV line): the kernels around the tile core of lz_spmv.h and their
+// launchers.
+#include <algorithm>
+#include <cmath>
+
+#include "lz_spmv.h"
+
+namespace lz {
+
+// ------------------------------------------------------------------- SpMV
+// Lanczos step SpMV (Algorithm 1, SpMV and alpha lines, and the beta term of
+// the three-term update): y = scale_j * (A V[:,j]); w = y - beta_j v_{j-1};
+// alpha_j = v_j . y.  In a restart iteration it draws the restart vector
+// into w instead.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
+                                                     typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
+                                                     int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
+                                                     uint32_t* tk, double* head, double* tail, double* part) {
+    using VT = typename Tr<P>::V;
+    using AT = typename Tr<P>::A;
+    using WT = typename Tr<P>::W;
+    __shared__ double shd[BLOCK / 64];
+    __shared__ int s_last;
+    if (st->status != 0) return;
+    const int j = st->j;
+    if (j >= st->m) return;
+    if (st->mode == MODE_RESTART) {
+        // Restart: a fresh random vector; the Gram-Schmidt kernels that follow
+        // orthogonalise it against the basis.
+        const uint64_t rs = st->seed + ((uint64_t)st->restarts << 32);
+        const int32_t* perm = st->perm;
+        for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < ld; r += (int64_t)gridDim.x * BLOCK)
+            w[r] = (WT)(r < n ? u01(rs, (uint64_t)(perm ? perm[r] : r)) : 0.0);
+        return;
+    }
+    const int64_t* rp = st->crp;
+    const int32_t* col = st->ccol;
+    const VT* val = (const VT*)st->cval;
+    const VT* x = Vb + (int64_t)j * ld;
+    const VT* xp = j > 0 ? Vb + (int64_t)(j - 1) * ld : nullptr;
+    const double sj = st->scale[j];
+    const double bsc = j > 0 ? st->beta[j] * st->scale[j - 1] : 0.0;
+    double apart = 0.0;
+    // alpha = sum_r (sj x_r)(sj acc_r) is linear in every row sum, so a split
+    // row adds one term per piece and the w update waits for the whole sum.
+    spmv_tiles<VT, VT, AT>(
+        rp, col, val, x, n, nnz, n_tiles, ob, tk, head, tail,
+        [&](int64_t r, double acc) {
+            const double y = sj * acc;
+            apart += sj * to_d(x[r]) * y;
+            w[r] = (WT)(y - (xp ? bsc * to_d(xp[r]) : 0.0));
+        },
+        [&](int64_t r, double acc) { apart += sj * to_d(x[r]) * (sj * acc); },
+        [&](int64_t r, double acc) { w[r] = (WT)(sj * acc - (xp ? bsc * to_d(xp[r]) : 0.0)); });
+    apart = block_sum(apart, shd);
+    if (threadIdx.x == 0) st_dev(&part[blockIdx.x], apart);
+    if (last_block(&st->ticket[TK_SPMV], gridDim.x, &s_last)) {
+        const double alpha = ordered_sum_dev(part, gridDim.x, shd);
+        if (threadIdx.x == 0) {
+            st->alpha[j] = alpha;
+            if (st->reorth == 0) {          // three-term recurrence only
+                st->c2[j] = alpha;
+                st->second = 1;
+            }
+        }
+    }
+}
+
+// Plain y = A x (component entry point), same tiles and kernel core.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      const typename Tr<P>::V* __restrict__ val,
+                                                      const typename Tr<P>::V* __restrict__ x,
+                                                      typename Tr<P>::W* __restrict__ y, int64_t n, int64_t nnz,
+                                                      int64_t n_tiles, const int32_t* __restrict__ ob, uint32_t* tk,
+                                                      double* head, double* tail) {
+    using VT = typename Tr<P>::V;
+    using AT = typename Tr<P>::A;
+    using WT = typename Tr<P>::W;
+    if (st->status != 0) return;
+    spmv_tiles<VT, VT, AT>(
+        rp, col, val, x, n, nnz, n_tiles, ob, tk, head, tail, [&](int64_t r, double acc) { y[r] = (WT)acc; },
+        [&](int64_t, double) {}, [&](int64_t r, double acc) { y[r] = (WT)acc; });
+}
+
+// ---------------------------------------------------------------- launchers
+template <int P>
+static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
+    using VT = typename Tr<P>::V;
+    using WT = typename Tr<P>::W;
+    hipLaunchKernelGGL((k_spmv_step<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V, (WT*)b.w, a.n,
+                       a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+}
+
+void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
+    switch (p.prec) {
+        case 0: spmv_step_p<0>(p, b, a, s); break;
+        case 1: spmv_step_p<1>(p, b, a, s); break;
+        default: spmv_step_p<2>(p, b, a, s); break;
+    }
+}
+
+template <int P>
+static void spmv_plain_p(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y, hipStream_t s) {
+    using VT = typename Tr<P>::V;
+    using WT = typename Tr<P>::W;
+    hipLaunchKernelGGL((k_spmv_plain<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                       (const VT*)a.val, (const VT*)x, (WT*)y, a.n, a.nnz, p.n_tiles, b.ob, b.tk, b.head, b.tail);
+}
+
+hipError_t launch_spmv_plain(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y, hipStream_t s) {
+    switch (p.prec) {
+        case 0: spmv_plain_p<0>(p, b, a, x, y, s); break;
+        case 1: spmv_plain_p<1>(p, b, a, x, y, s); break;
+        case 2: spmv_plain_p<2>(p, b, a, x, y, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lz
