@@ -164,10 +164,10 @@ def serving_requests(pool, n_req: int, seed: int = 1):
     return reqs
 
 
-def run_stream(lz, pool_dev, reqs, arrivals, force_prec, budget, slots):
+def run_stream(lz, pool_dev, reqs, arrivals, force_prec, budget, slots, graphs=True):
     """Submits requests at their arrival times (seconds from start) and waits
     for all.  Returns (elapsed_s, latencies_ms, results by index)."""
-    srv = lz.Server(budget, max_slots=slots, use_graphs=True)
+    srv = lz.Server(budget, max_slots=slots, use_graphs=graphs)
     try:
         t0 = time.perf_counter()
         tickets = []
@@ -210,7 +210,7 @@ def serving_main(args):
     burst = np.zeros(len(reqs))
     runs = {}
     for name, force in (("fp64", "fp64"), ("fp32", "fp32"), ("mix", None)):
-        el, lat, out, st = run_stream(lz, pool_dev, reqs, burst, force, budget, args.slots)
+        el, lat, out, st = run_stream(lz, pool_dev, reqs, burst, force, budget, args.slots, not args.no_graphs)
         runs[name] = dict(elapsed=el, lat=lat, out=out, stats=st)
         print(f"[serving] saturation {name}: {len(reqs) / el:.1f} solves/s, p50 {np.percentile(lat, 50):.1f} ms, "
               f"p99 {np.percentile(lat, 99):.1f} ms, arena peak {st['arena_peak'] / 2**30:.1f} GiB",
@@ -218,10 +218,10 @@ def serving_main(args):
     # Poisson arrivals of the mix at fractions of the measured FP64 capacity.
     cap = len(reqs) / runs["fp64"]["elapsed"]
     sweep = []
-    for frac in (0.5, 0.8, 1.0, 1.5):
+    for frac in (() if args.saturation_only else (0.5, 0.8, 1.0, 1.5)):
         rate = frac * cap
         arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, len(reqs)))
-        el, lat, out, st = run_stream(lz, pool_dev, reqs, arr, None, budget, args.slots)
+        el, lat, out, st = run_stream(lz, pool_dev, reqs, arr, None, budget, args.slots, not args.no_graphs)
         sweep.append({"rate_per_s": rate, "fraction_of_fp64_capacity": frac, "solves_per_s": len(reqs) / el,
                       "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}})
         print(f"[serving] poisson mix at {rate:.1f} req/s ({frac}x FP64 capacity): {len(reqs) / el:.1f} solves/s, "
@@ -249,7 +249,8 @@ def serving_main(args):
         "data": "synthetic",
         "config": {"workload": "serving", "description": "request stream: R-MAT/ER, n log-uniform in [1e4, 2e6], "
                    "degree U[4,32], K in {4,8,16}, m=3K", "requests": len(reqs), "pool": len(pool),
-                   "slots": args.slots, "budget_gb": args.budget_gb, "parallelism": "single-gpu"},
+                   "slots": args.slots, "graphs": not args.no_graphs, "budget_gb": args.budget_gb,
+                   "parallelism": "single-gpu"},
         "fp32": f(runs["fp32"]), "fp64": f(runs["fp64"]), "mix": f(runs["mix"]),
         "poisson_mix": sweep,
         "speedup_fp32_vs_fp64": runs["fp64"]["elapsed"] / runs["fp32"]["elapsed"],
@@ -270,6 +271,8 @@ def main():
     ap.add_argument("--pool", type=int, default=32, help="serving: distinct matrices")
     ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM arena")
+    ap.add_argument("--no-graphs", action="store_true", help="serving: launch kernels directly, no hipGraph")
+    ap.add_argument("--saturation-only", action="store_true", help="serving: skip the Poisson arrival sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy kernel (1 GiB read + 1 GiB written, three launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic of the other kernels")

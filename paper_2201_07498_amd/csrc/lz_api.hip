@@ -156,7 +156,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
     if (opt) o = *opt;
     if (o.reorth < LZ_REORTH_NONE || o.reorth > LZ_REORTH_SELECTIVE) return LZ_ERR_INVALID_ARG;
     if (o.reorder < LZ_REORDER_OFF || o.reorder > LZ_REORDER_AUTO) return LZ_ERR_INVALID_ARG;
-    const Plan p = make_plan(n, nnz, K, m, precision);
+    Plan p = make_plan(n, nnz, K, m, precision);
     if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
 
     hipStream_t s = (hipStream_t)stream;
@@ -196,6 +196,12 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             LZ_HIP(hipEventRecord(pev[0], s));
         }
         LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, o.reorder, s));
+        if (o.reorder != LZ_REORDER_OFF && want_xcache(p, true)) {
+            // The SpMV variant depends on the row order the device chose.
+            LZ_HIP(hipMemcpyAsync(hst, b.st, offsetof(State, maxdeg), hipMemcpyDeviceToHost, s));
+            LZ_HIP(hipStreamSynchronize(s));
+            p.xcache = want_xcache(p, hst->reordered != 0);
+        }
         LZ_HIP(launch_init(p, b, s));
         if (o.profile) LZ_HIP(hipEventRecord(pev[1], s));
         for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, o.reorth, s, iter_events(t)));

@@ -73,6 +73,7 @@ struct Plan {
     int64_t n = 0, nnz = 0, ld = 0;
     int32_t K = 0, m = 0, prec = 0, KB = 0;
     int32_t g_orth = 0, g_tile = 0;
+    int32_t xcache = 0;         // Lanczos-step SpMV keeps the head of x in LDS (set once the row order is known)
     int64_t n_tiles = 0;
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
            off_Y = 0, off_Z = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0, off_tail = 0, off_rp2 = 0,
@@ -137,6 +138,19 @@ hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncol
                             hipStream_t s, hipEvent_t* ev = nullptr);
 // The Lanczos-step SpMV of the current iteration (or its restart draw).
 void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s);
+// The LDS copy of the head of x pays off for relabelled (power-law)
+// matrices in the mixed modes and costs occupancy elsewhere.  Measured on
+// MI355X: R-MAT scale 23 FP32 1.79 -> 1.59 ms, BF16 1.63 -> 1.25 ms; scale
+// 20 BF16 90 -> 80 us but FP32 102 -> 105 us; banded FP32 0.77 -> 1.15 ms.
+inline bool want_xcache(const Plan& p, bool relabelled) {
+    if (!relabelled) return false;
+    if (p.prec == 2) return p.n >= (int64_t(1) << 20);
+    if (p.prec == 1) return p.n >= (int64_t(1) << 22);
+    return false;
+}
+// The relabelling decision of the setup kernels, for callers that hold the
+// row pointer on the host (same integer test as on the device).
+bool host_relabel_decision(const int64_t* rowptr_host, int64_t n, int64_t nnz, int reorder);
 hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
                          double* out_vecs, int report, hipStream_t s);
 hipError_t launch_spmv_plain(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y,

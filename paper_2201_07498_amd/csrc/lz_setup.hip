@@ -318,6 +318,15 @@ __global__ __launch_bounds__(BLOCK) void k_setup_tiles(const State* st, int64_t 
     }
 }
 
+bool host_relabel_decision(const int64_t* rp, int64_t n, int64_t nnz, int reorder) {
+    if (n <= 1 || nnz <= 0 || reorder == LZ_REORDER_OFF) return false;
+    if (reorder == LZ_REORDER_HUBS) return true;
+    if (n < REORDER_MIN_N) return false;
+    int64_t mx = 0;
+    for (int64_t r = 0; r < n; ++r) mx = std::max<int64_t>(mx, rp[r + 1] - rp[r]);
+    return (double)mx * (double)n >= REORDER_SKEW * (double)nnz;
+}
+
 hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth, int reorder,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, b.st, p.m, p.K, reorth, reorder, unit_roundoff(p.prec),

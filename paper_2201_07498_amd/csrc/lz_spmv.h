@@ -100,13 +100,15 @@ __device__ __forceinline__ AT lds_wave_sum(const AT* p, int b, int e, int lane) 
 struct TileRange {
     int64_t first, end, stride;
 };
+template <int NW = WAVES>
 __device__ __forceinline__ TileRange wave_tiles(int64_t n_tiles) {
     const int64_t xcd = blockIdx.x & 7, nb8 = gridDim.x >> 3;
     const int64_t lo = n_tiles * xcd / 8, hi = n_tiles * (xcd + 1) / 8;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t w = (int64_t)(blockIdx.x >> 3) * WAVES + wave;
-    return {lo + w, hi, nb8 * WAVES};
+    const int64_t w = (int64_t)(blockIdx.x >> 3) * NW + wave;
+    return {lo + w, hi, nb8 * NW};
 }
+
 
 // Adds the pieces of the split row r (tail pieces in tiles t1..t2-1, head
 // piece in t2) in tile order; called by every lane of the finalising
@@ -119,16 +121,18 @@ __device__ __forceinline__ double split_total(const double* head, const double* 
     return s + ld_dev(&head[t2]);
 }
 
-template <class VT, class XT, class AT, class Row, class Piece, class Fin>
+// NW wavefronts per workgroup.  With CACHED, xs holds x[0..hn) in LDS and
+// gathers of those entries read it instead of global memory.
+template <class VT, class AT, int NW, bool CACHED, class Row, class Piece, class Fin>
 __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                           const VT* __restrict__ val, const XT* __restrict__ x, int64_t n,
-                                           int64_t nnz, int64_t n_tiles, const int32_t* __restrict__ ob,
-                                           uint32_t* tk, double* head, double* tail, Row&& row, Piece&& piece,
-                                           Fin&& fin) {
-    __shared__ AT prod[WAVES][TILE];
+                                           const VT* __restrict__ val, const VT* __restrict__ x, const VT* xs,
+                                           int hn, int64_t n, int64_t nnz, int64_t n_tiles,
+                                           const int32_t* __restrict__ ob, uint32_t* tk, double* head, double* tail,
+                                           Row&& row, Piece&& piece, Fin&& fin) {
+    __shared__ AT prod[NW][TILE];
     const int lane = threadIdx.x & 63;
     AT* pw = prod[threadIdx.x >> 6];
-    const TileRange tr = wave_tiles(n_tiles);
+    const TileRange tr = wave_tiles<NW>(n_tiles);
     const int64_t items = nnz + n;
     int64_t r_lo = 0, r_hi = 0;
     if (tr.first < tr.end) {
@@ -158,7 +162,14 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
                 vv[q] = val[p];
             }
 #pragma unroll
-            for (int q = 0; q < TP; ++q) pw[q * 64 + lane] = to_a(vv[q], AT(0)) * to_a(x[ci[q]], AT(0));
+            for (int q = 0; q < TP; ++q) {
+                VT xv;
+                if constexpr (CACHED)
+                    xv = ci[q] < hn ? xs[ci[q]] : x[ci[q]];
+                else
+                    xv = x[ci[q]];
+                pw[q * 64 + lane] = to_a(vv[q], AT(0)) * to_a(xv, AT(0));
+            }
         }
         wave_sync();
         // Owned rows, 64 at a time.

@@ -13,16 +13,26 @@ namespace lz {
 // the three-term update): y = scale_j * (A V[:,j]); w = y - beta_j v_{j-1};
 // alpha_j = v_j . y.  In a restart iteration it draws the restart vector
 // into w instead.
-template <int P>
-__global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
-                                                     typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
-                                                     int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
-                                                     uint32_t* tk, double* head, double* tail, double* part) {
+// Cached variant (mixed modes, large relabelled matrices): a workgroup of XW
+// wavefronts first copies the head of x (the first XC_BYTES) into LDS.  After
+// the hub-first relabelling the most frequently gathered entries sit there
+// (on R-MAT scale 23 the first 16K columns take a third of all gathers), so
+// those gathers skip L1 and L2.
+constexpr int XW = 16;                 // wavefronts per workgroup of the cached variant
+constexpr int XC_BYTES = 64 * 1024;
+
+template <int P, int NW, bool XCACHE>
+__global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
+                                                       typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
+                                                       int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
+                                                       uint32_t* tk, double* head, double* tail, double* part) {
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
-    __shared__ double shd[BLOCK / 64];
+    constexpr int H = XCACHE ? XC_BYTES / (int)sizeof(VT) : 1;
+    __shared__ double shd[NW];
     __shared__ int s_last;
+    __shared__ VT xs[H];
     if (st->status != 0) return;
     const int j = st->j;
     if (j >= st->m) return;
@@ -31,7 +41,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const typename T
         // orthogonalise it against the basis.
         const uint64_t rs = st->seed + ((uint64_t)st->restarts << 32);
         const int32_t* perm = st->perm;
-        for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < ld; r += (int64_t)gridDim.x * BLOCK)
+        for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += (int64_t)gridDim.x * blockDim.x)
             w[r] = (WT)(r < n ? u01(rs, (uint64_t)(perm ? perm[r] : r)) : 0.0);
         return;
     }
@@ -45,16 +55,21 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_step(State* st, const typename T
     double apart = 0.0;
     // alpha = sum_r (sj x_r)(sj acc_r) is linear in every row sum, so a split
     // row adds one term per piece and the w update waits for the whole sum.
-    spmv_tiles<VT, VT, AT>(
-        rp, col, val, x, n, nnz, n_tiles, ob, tk, head, tail,
-        [&](int64_t r, double acc) {
-            const double y = sj * acc;
-            apart += sj * to_d(x[r]) * y;
-            w[r] = (WT)(y - (xp ? bsc * to_d(xp[r]) : 0.0));
-        },
-        [&](int64_t r, double acc) { apart += sj * to_d(x[r]) * (sj * acc); },
-        [&](int64_t r, double acc) { w[r] = (WT)(sj * acc - (xp ? bsc * to_d(xp[r]) : 0.0)); });
-    apart = block_sum(apart, shd);
+    auto row = [&](int64_t r, double acc) {
+        const double y = sj * acc;
+        apart += sj * to_d(x[r]) * y;
+        w[r] = (WT)(y - (xp ? bsc * to_d(xp[r]) : 0.0));
+    };
+    auto piece = [&](int64_t r, double acc) { apart += sj * to_d(x[r]) * (sj * acc); };
+    auto fin = [&](int64_t r, double acc) { w[r] = (WT)(sj * acc - (xp ? bsc * to_d(xp[r]) : 0.0)); };
+    int hn = 0;
+    if constexpr (XCACHE) {
+        hn = (int)min<int64_t>(H, n);
+        for (int i = threadIdx.x; i < hn; i += NW * 64) xs[i] = x[i];
+        __syncthreads();
+    }
+    spmv_tiles<VT, AT, NW, XCACHE>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, row, piece, fin);
+    apart = block_sum(apart, shd, NW);
     if (threadIdx.x == 0) st_dev(&part[blockIdx.x], apart);
     if (last_block(&st->ticket[TK_SPMV], gridDim.x, &s_last)) {
         const double alpha = ordered_sum_dev(part, gridDim.x, shd);
@@ -81,8 +96,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
     if (st->status != 0) return;
-    spmv_tiles<VT, VT, AT>(
-        rp, col, val, x, n, nnz, n_tiles, ob, tk, head, tail, [&](int64_t r, double acc) { y[r] = (WT)acc; },
+    spmv_tiles<VT, AT, WAVES, false>(
+        rp, col, val, x, nullptr, 0, n, nnz, n_tiles, ob, tk, head, tail, [&](int64_t r, double acc) { y[r] = (WT)acc; },
         [&](int64_t, double) {}, [&](int64_t r, double acc) { y[r] = (WT)acc; });
 }
 
@@ -91,8 +106,19 @@ template <int P>
 static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
     using VT = typename Tr<P>::V;
     using WT = typename Tr<P>::W;
-    hipLaunchKernelGGL((k_spmv_step<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V, (WT*)b.w, a.n,
-                       a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+    if constexpr (P == 0) {
+        hipLaunchKernelGGL((k_spmv_step<P, WAVES, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V,
+                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+    } else if (!p.xcache) {
+        hipLaunchKernelGGL((k_spmv_step<P, WAVES, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V,
+                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+    } else {
+        // One workgroup of XW wavefronts per CU (its LDS holds the x head).
+        const int64_t g = std::min<int64_t>(256, (p.n_tiles + XW - 1) / XW);
+        const int gx = (int)((g + 7) / 8 * 8);
+        hipLaunchKernelGGL((k_spmv_step<P, XW, true>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
+                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+    }
 }
 
 void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
