@@ -167,16 +167,20 @@ __device__ __forceinline__ void publish_split(const double (&acc)[NCL], int nc, 
                (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]));
 }
 
-// out[k] = mul[k] * sum_b part[b*NCMAX + k] over the nb workgroup rows, in a
-// fixed order (thread t owns rows t, t+BLOCK, ...; then a fixed tree).
+// out[k] = mul[k] * sum_b part[b*NCMAX + k] over the nb workgroup rows, and
+// the sum of the scalar partials p2[b], in a fixed order (thread t owns rows
+// t, t+BLOCK, ...; then a fixed tree).  Both sets of partials are loaded in
+// the same pass, so the last workgroup waits for one round of loads.
 template <int NC>
-__device__ __forceinline__ void reduce_columns(const double* part, int nb, int nc, const double* mul, double* out,
-                                               double (*red)[NC]) {
+__device__ __forceinline__ double reduce_columns(const double* part, const double* p2, int nb, int nc,
+                                                 const double* mul, double* out, double (*red)[NC], double* sh) {
     double acc[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) acc[k] = 0.0;
+    double s2 = 0.0;
     for (int b = threadIdx.x; b < nb; b += BLOCK) {
         const double* pr = part + (int64_t)b * NCMAX;
+        s2 += ld_dev(p2 + b);
 #pragma unroll
         for (int k = 0; k < NC; ++k)
             if (k < nc) acc[k] += ld_dev(pr + k);
@@ -189,11 +193,15 @@ __device__ __forceinline__ void reduce_columns(const double* part, int nb, int n
             const double v = wave_sum(acc[k]);
             if (ln == 0) red[wv][k] = v;
         }
+    s2 = wave_sum(s2);
+    if (ln == 0) sh[wv] = s2;
     __syncthreads();
     if ((int)threadIdx.x < nc)
         out[threadIdx.x] =
             mul[threadIdx.x] * ((red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]));
+    const double tot = (sh[0] + sh[1]) + (sh[2] + sh[3]);
     __syncthreads();
+    return tot;
 }
 
 // c = V[:,0..j]^T w (coefficients with respect to the unit basis vectors).
@@ -252,8 +260,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
     nrm = block_sum(nrm, shd);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_DOT], gridDim.x, &s_last)) {
-        reduce_columns<NC>(part, gridDim.x, nc, st->scale, st->c, red);
-        const double wn = ordered_sum_dev(part2, gridDim.x, shd);
+        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c, red, shd);
         if (gram_mode(st)) {
             // Second coefficients of classical Gram-Schmidt without a second
             // pass: V^T (w - V c) = c - G c, G the Gram matrix of the unit
@@ -280,6 +287,11 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
             if (threadIdx.x == 0) {
                 st->wnorm2 = w1;
                 st->second = 1;
+                // alpha_j = v_j . A v_j = c_j + beta_j (v_j . v_{j-1}), with
+                // w = A v_j - beta_j v_{j-1}; the SpMV does not reduce it in
+                // these modes.
+                if (st->mode == MODE_NORMAL)
+                    st->alpha[j] = sc[j] + (j > 0 ? st->beta[j] * gm[j * NCMAX + (j - 1)] : 0.0);
             }
         } else if (!upd_dot_active(st)) {  // one pass: the store kernel uses c
             for (int k = threadIdx.x; k < nc; k += BLOCK) st->c2[k] = st->c[k];
@@ -377,8 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typenam
     nrm = block_sum(nrm, shd);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_UPD], gridDim.x, &s_last)) {
-        reduce_columns<NC>(part, gridDim.x, nc, st->scale, st->c2, red);
-        const double wn = ordered_sum_dev(part2, gridDim.x, shd);
+        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c2, red, shd);
         if (threadIdx.x == 0) {
             st->wnorm2 = wn;
             int second = 1;
@@ -476,8 +487,8 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
     nrm = block_sum(nrm, shd);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_STORE], gridDim.x, &s_last)) {
-        if (gram) reduce_columns<NC>(part, gridDim.x, nc, st->scale, gcol, red);
-        const double tot = ordered_sum_dev(part2, gridDim.x, shd);
+        const double tot = gram ? reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, gcol, red, shd)
+                                : ordered_sum_dev(part2, gridDim.x, shd);
         if (threadIdx.x == 0) {
             const double b = sqrt(tot);
             int accept = 0;

@@ -11,8 +11,8 @@ namespace lz {
 // ------------------------------------------------------------------- SpMV
 // Lanczos step SpMV (Algorithm 1, SpMV and alpha lines, and the beta term of
 // the three-term update): y = scale_j * (A V[:,j]); w = y - beta_j v_{j-1};
-// alpha_j = v_j . y.  In a restart iteration it draws the restart vector
-// into w instead.
+// alpha_j = v_j . y in the one-pass modes.  In a restart iteration it draws
+// the restart vector into w instead.
 // Cached variant (mixed modes, large relabelled matrices): a workgroup of XW
 // wavefronts first copies the head of x (the first XC_BYTES) into LDS.  After
 // the hub-first relabelling the most frequently gathered entries sit there
@@ -55,12 +55,17 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
     double apart = 0.0;
     // alpha = sum_r (sj x_r)(sj acc_r) is linear in every row sum, so a split
     // row adds one term per piece and the w update waits for the whole sum.
+    // In the two-pass modes alpha comes from the first Gram-Schmidt pass
+    // (alpha_j = c_j + beta_j v_j . v_{j-1}); only the other modes reduce it here.
+    const bool need_alpha = st->reorth < 2;
     auto row = [&](int64_t r, double acc) {
         const double y = sj * acc;
-        apart += sj * to_d(x[r]) * y;
+        if (need_alpha) apart += sj * to_d(x[r]) * y;
         w[r] = (WT)(y - (xp ? bsc * to_d(xp[r]) : 0.0));
     };
-    auto piece = [&](int64_t r, double acc) { apart += sj * to_d(x[r]) * (sj * acc); };
+    auto piece = [&](int64_t r, double acc) {
+        if (need_alpha) apart += sj * to_d(x[r]) * (sj * acc);
+    };
     auto fin = [&](int64_t r, double acc) { w[r] = (WT)(sj * acc - (xp ? bsc * to_d(xp[r]) : 0.0)); };
     int hn = 0;
     if constexpr (XCACHE) {
@@ -69,6 +74,7 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
         __syncthreads();
     }
     spmv_tiles<VT, AT, NW, XCACHE>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, row, piece, fin);
+    if (!need_alpha) return;
     apart = block_sum(apart, shd, NW);
     if (threadIdx.x == 0) st_dev(&part[blockIdx.x], apart);
     if (last_block(&st->ticket[TK_SPMV], gridDim.x, &s_last)) {
