@@ -30,7 +30,8 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.ld = ceil_div(n, LDPAD) * LDPAD;
     if ((p.ld / LDPAD) % 2 == 0) p.ld += LDPAD;
     p.KB = (int32_t)std::max<int64_t>(8, ceil_div(K, 8) * 8);
-    p.g_orth = (int32_t)std::min<int64_t>(OGRID, p.ld / BLOCK);
+    p.g_orth = (int32_t)std::min<int64_t>(OGRID, p.ld / OBLOCK);
+    p.g_dense = (int32_t)std::min<int64_t>(DGRID, p.ld / BLOCK);
     p.n_tiles = ceil_div(nnz + n, TILE);
     // Tiled SpMV grid: a multiple of 8 workgroups (one share per XCD).
     p.g_tile = (int32_t)(ceil_div(std::min<int64_t>(SGRID, ceil_div(p.n_tiles, 4)), 8) * 8);
@@ -47,8 +48,8 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_state = take(sizeof(State));
     p.off_V = take((size_t)p.ld * (size_t)(m + 1) * vb);
     p.off_w = take((size_t)p.ld * wb);
-    p.off_part = take((size_t)std::max(p.g_orth, 1024) * 256 * 8);
-    p.off_part2 = take((size_t)std::max(std::max(p.g_tile, p.g_orth), 2048) * 64 * 8);
+    p.off_part = take((size_t)std::max(p.g_dense, 1024) * 256 * 8);
+    p.off_part2 = take((size_t)std::max(std::max(p.g_tile, p.g_dense), 2048) * 64 * 8);
     p.off_scan = take((size_t)scan_n * 8);
     p.off_bsum = take((size_t)(ceil_div(scan_n, 2048) + 2) * 8);
     p.off_Y = take((size_t)n * (size_t)K * 8);

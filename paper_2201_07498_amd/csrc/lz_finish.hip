@@ -699,7 +699,7 @@ static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* o
     switch (p.KB) {
 #define LZ_RITZ_CASE(KBV)                                                                                    \
     case KBV:                                                                                                \
-        hipLaunchKernelGGL((k_ritz<P, KBV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, p.n, p.ld, b.Y);  \
+        hipLaunchKernelGGL((k_ritz<P, KBV>), dim3(p.g_dense), dim3(BLOCK), 0, s, b.st, V, p.n, p.ld, b.Y);  \
         break;
         LZ_RITZ_CASE(8)
         LZ_RITZ_CASE(16)

@@ -15,7 +15,9 @@ constexpr int NCMAX = 72;      // column bound of the orthogonalisation kernels 
 constexpr int BLOCK = 256;     // threads per workgroup (4 wave64)
 constexpr int TILE = 1024;     // non-zeros per SpMV tile (one wavefront, 16 per lane)
 constexpr int LDPAD = 2048;    // basis leading dimension is a multiple of this
-constexpr int OGRID = 1024;    // orthogonalisation grid cap (workgroups)
+constexpr int OGRID = 256;     // orthogonalisation grid cap (workgroups of OBLOCK threads)
+constexpr int OBLOCK = 1024;   // orthogonalisation workgroup (16 wave64)
+constexpr int DGRID = 1024;    // grid cap of the other dense kernels (workgroups of BLOCK threads)
 constexpr int SGRID = 2048;    // SpMV grid cap (workgroups)
 constexpr int GRAM_PARTS = 1024; // Gram kernel grid cap (per-workgroup 64x64 partials)
 
@@ -72,7 +74,7 @@ static_assert(offsetof(State, status) + sizeof(int32_t) <= STATE_HEAD_BYTES, "st
 struct Plan {
     int64_t n = 0, nnz = 0, ld = 0;
     int32_t K = 0, m = 0, prec = 0, KB = 0;
-    int32_t g_orth = 0, g_tile = 0;
+    int32_t g_orth = 0, g_dense = 0, g_tile = 0;
     int32_t xcache = 0;         // Lanczos-step SpMV keeps the head of x in LDS (set once the row order is known)
     int64_t n_tiles = 0;
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
@@ -97,7 +99,7 @@ struct Bufs {
     State* st;
     void* V;
     void* w;
-    double* part;      // per-workgroup partials: max(g_orth, 1024) * 256 doubles
+    double* part;      // per-workgroup partials: max(g_dense, 1024) * 256 doubles
     double* part2;     // second partial buffer (SpMV alpha, residual)
     uint64_t* scan;    // scan scratch (degree-class histogram)
     uint64_t* bsum;    // scan block sums

@@ -12,7 +12,7 @@
 // the classical second pass instead: k_orth_upd_dot, w' = w - V c and
 // c2 = V^T w', runs between the two.
 // Global sums are per-workgroup partials that the last workgroup to finish
-// adds in workgroup order, so results do not depend on scheduling.  The step
+// adds in a fixed order, so results do not depend on scheduling.  The step
 // index and every coefficient stay in device memory.
 //
 // The basis V is column-major with leading dimension ld (a multiple of
@@ -80,7 +80,7 @@ __device__ __forceinline__ bool upd_dot_active(const State* st) {
 // The dense kernels move 16-byte chunks: R consecutive rows of one basis
 // column (2 in FP64, 4 in FP32, 8 in BF16) and the matching R rows of w.
 // The columns of a step are split over CS adjacent lanes (NCL each), so a
-// lane keeps at most 16 chunks in registers; CS lanes together own a row
+// lane keeps at most 8 chunks in registers; CS lanes together own a row
 // group and combine their partial updates with shuffles.
 template <int P> struct Ch;
 template <> struct Ch<0> { typedef double2 T; static constexpr int R = 2; };
@@ -88,7 +88,7 @@ template <> struct Ch<1> { typedef float4 T; static constexpr int R = 4; };
 template <> struct Ch<2> { typedef uint4 T; static constexpr int R = 8; };
 
 template <int P, int NC> struct Split {
-    static constexpr int NCLMAX = P == 2 ? 8 : 16;     // chunks a lane keeps in registers
+    static constexpr int NCLMAX = 8;                   // chunks a lane keeps in registers
     static constexpr int CS = NC <= NCLMAX ? 1 : (NC <= 2 * NCLMAX ? 2 : (NC <= 4 * NCLMAX ? 4 : 8));
     static constexpr int NCL = NC / CS;
 };
@@ -148,9 +148,16 @@ __device__ __forceinline__ void v_round_store(uint16_t* v, double (&x)[8], bool 
     if (st) *(uint4*)v = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
 }
 
+// The orthogonalisation kernels run workgroups of OBLOCK threads (OWAVES
+// wavefronts), at most OGRID of them.  Each wavefront walks chunks of RBW =
+// (64 / CS) * R rows (at most 512, so a chunk never crosses ld, a multiple of
+// LDPAD), chunk index = global wavefront index, grid-strided.
+constexpr int OWAVES = OBLOCK / 64;
+
 // Wave sums of acc[kk] over the lanes that own the same columns (lane % CS
 // equal); lanes 0..CS-1 write them to red[wave][column].  Then thread k < nc
-// publishes the workgroup sum of column k to part[blockIdx.x*NCMAX + k].
+// publishes the workgroup sum of column k (wavefronts in order) to
+// part[blockIdx.x*NCMAX + k].
 template <int NC, int CS, int NCL>
 __device__ __forceinline__ void publish_split(const double (&acc)[NCL], int nc, double* part, double (*red)[NC]) {
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, cs = ln % CS;
@@ -162,59 +169,63 @@ __device__ __forceinline__ void publish_split(const double (&acc)[NCL], int nc, 
         if (ln < CS) red[wv][cs * NCL + kk] = v;
     }
     __syncthreads();
-    if ((int)threadIdx.x < nc)
-        st_dev(&part[(int64_t)blockIdx.x * NCMAX + threadIdx.x],
-               (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]));
+    if ((int)threadIdx.x < nc) {
+        double s = red[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < OWAVES; ++q) s += red[q][threadIdx.x];
+        st_dev(&part[(int64_t)blockIdx.x * NCMAX + threadIdx.x], s);
+    }
 }
 
-// out[k] = mul[k] * sum_b part[b*NCMAX + k] over the nb workgroup rows, and
-// the sum of the scalar partials p2[b], in a fixed order (thread t owns rows
-// t, t+BLOCK, ...; then a fixed tree).  Both sets of partials are loaded in
-// the same pass, so the last workgroup waits for one round of loads.
+// Run by the last workgroup: out[k] = mul[k] * sum_b part[b*NCMAX + k] for
+// k < nc over the nb <= OGRID workgroup rows; returns sum_b p2[b].  Thread t
+// owns column t % (NC+1) (column NC stands for p2) in slice t / (NC+1), i.e.
+// rows slice, slice + S, slice + 2S, ... (S slices).  Its loads do not depend
+// on one another and are all issued before the first add, so the workgroup
+// waits for one round of loads.  The S slice sums of a column are then added
+// in slice order: the result depends on nb only, not on scheduling.
 template <int NC>
 __device__ __forceinline__ double reduce_columns(const double* part, const double* p2, int nb, int nc,
-                                                 const double* mul, double* out, double (*red)[NC], double* sh) {
-    double acc[NC];
+                                                 const double* mul, double* out, double* sred, double* sh) {
+    constexpr int NCC = NC + 1, S = OBLOCK / NCC, RPT = (OGRID + S - 1) / S;
+    static_assert(NC <= NCMAX && S >= 1, "column count");
+    const int t = threadIdx.x, col = t % NCC, slice = t / NCC;
+    if (slice < S) {
+        const double* src = col < NC ? part + col : p2;
+        const int64_t stride = col < NC ? NCMAX : 1;
+        double v[RPT];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) acc[k] = 0.0;
-    double s2 = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BLOCK) {
-        const double* pr = part + (int64_t)b * NCMAX;
-        s2 += ld_dev(p2 + b);
+        for (int i = 0; i < RPT; ++i) v[i] = ld_dev(src + (int64_t)min(slice + i * S, nb - 1) * stride);
+        double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (k < nc) acc[k] += ld_dev(pr + k);
+        for (int i = 0; i < RPT; ++i) s += slice + i * S < nb ? v[i] : 0.0;
+        sred[t] = s;
     }
     __syncthreads();
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < NC; ++k)
-        if (k < nc) {
-            const double v = wave_sum(acc[k]);
-            if (ln == 0) red[wv][k] = v;
-        }
-    s2 = wave_sum(s2);
-    if (ln == 0) sh[wv] = s2;
+    if (t < NCC) {
+        double s = sred[t];
+        for (int q = 1; q < S; ++q) s += sred[q * NCC + t];
+        if (t < nc) out[t] = mul[t] * s;
+        if (t == NC) sh[0] = s;
+    }
     __syncthreads();
-    if ((int)threadIdx.x < nc)
-        out[threadIdx.x] =
-            mul[threadIdx.x] * ((red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]));
-    const double tot = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    const double tot = sh[0];
     __syncthreads();
     return tot;
 }
 
 // c = V[:,0..j]^T w (coefficients with respect to the unit basis vectors).
 template <int P, int NC>
-__global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
+__global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                     const typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                     double* part, double* part2, const double* __restrict__ gm) {
     using VT = typename Tr<P>::V;
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
-    __shared__ double red[BLOCK / 64][NC];
+    __shared__ double red[OWAVES][NC];
     __shared__ double sc[NC];
-    __shared__ double shd[BLOCK / 64];
+    __shared__ double shd[OWAVES];
+    __shared__ double sred[OBLOCK];
     __shared__ int s_last;
     const int j = st->j;
     if (st->status != 0 || j >= st->m || !dot_active(st)) return;
@@ -224,14 +235,15 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
         return;
     }
     const int ln = threadIdx.x & 63, cs = ln % CS;
-    const int64_t rowgrp = (int64_t)(threadIdx.x >> 6) * GPW + ln / CS;
-    constexpr int64_t RB = (int64_t)(BLOCK / 64) * GPW * R;
+    constexpr int64_t RBW = (int64_t)GPW * R;
+    const int64_t lane_row = (int64_t)(ln / CS) * R;
+    const int64_t wave0 = (int64_t)blockIdx.x * OWAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double acc[NCL];
 #pragma unroll
     for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
     double nrm = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
-        const int64_t r0 = base + rowgrp * R;
+    for (int64_t base = wave0 * RBW; base < ld; base += (int64_t)gridDim.x * OWAVES * RBW) {
+        const int64_t r0 = base + lane_row;
         double x[R];
         w_load(w + r0, x);
         if (cs == 0)
@@ -257,16 +269,16 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
         }
     }
     publish_split<NC, CS, NCL>(acc, nc, part, red);
-    nrm = block_sum(nrm, shd);
+    nrm = block_sum(nrm, shd, OWAVES);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_DOT], gridDim.x, &s_last)) {
-        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c, red, shd);
+        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c, sred, shd);
         if (gram_mode(st)) {
             // Second coefficients of classical Gram-Schmidt without a second
             // pass: V^T (w - V c) = c - G c, G the Gram matrix of the unit
             // stored basis.  The update then subtracts V (c + c2) at once, in
             // FP64 registers, so no rounded intermediate w' exists.
-            for (int k = threadIdx.x; k < nc; k += BLOCK) sc[k] = st->c[k];
+            for (int k = threadIdx.x; k < nc; k += OBLOCK) sc[k] = st->c[k];
             __syncthreads();
             double c2 = 0.0;
             if ((int)threadIdx.x < nc) {
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
             double sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : 0.0,
                              (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : 0.0,
                              (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : 0.0};
-            for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd);
+            for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
             const double w1 = fmax(0.0, wn - 2.0 * sel[1] + sel[2]);
             const bool corr = st->reorth == 2 || st->mode == MODE_RESTART || sel[0] > st->u_s * st->u_s * w1;
             if ((int)threadIdx.x < nc) st->c2[threadIdx.x] = sc[threadIdx.x] + (corr ? c2 : 0.0);
@@ -294,7 +306,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_dot(State* st, const typename Tr
                     st->alpha[j] = sc[j] + (j > 0 ? st->beta[j] * gm[j * NCMAX + (j - 1)] : 0.0);
             }
         } else if (!upd_dot_active(st)) {  // one pass: the store kernel uses c
-            for (int k = threadIdx.x; k < nc; k += BLOCK) st->c2[k] = st->c[k];
+            for (int k = threadIdx.x; k < nc; k += OBLOCK) st->c2[k] = st->c[k];
             if (threadIdx.x == 0) st->second = 1;
         }
     }
@@ -327,14 +339,15 @@ __device__ __forceinline__ void split_update(const typename Ch<P>::T (&ch)[Split
 
 // w' = w - V c (stored in the working precision), then c2 = V^T w' and ||w'||^2.
 template <int P, int NC>
-__global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
+__global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                         typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                         double* part, double* part2) {
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
     __shared__ double coef[NC];
-    __shared__ double red[BLOCK / 64][NC];
-    __shared__ double shd[BLOCK / 64];
+    __shared__ double red[OWAVES][NC];
+    __shared__ double shd[OWAVES];
+    __shared__ double sred[OBLOCK];
     __shared__ int s_last;
     const int j = st->j;
     if (st->status != 0 || j >= st->m || !upd_dot_active(st)) return;
@@ -343,17 +356,18 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typenam
         if (blockIdx.x == 0 && threadIdx.x == 0) st->status = -1;
         return;
     }
-    for (int k = threadIdx.x; k < NC; k += BLOCK) coef[k] = k < nc ? st->c[k] * st->scale[k] : 0.0;
+    for (int k = threadIdx.x; k < NC; k += OBLOCK) coef[k] = k < nc ? st->c[k] * st->scale[k] : 0.0;
     __syncthreads();
     const int ln = threadIdx.x & 63, cs = ln % CS;
-    const int64_t rowgrp = (int64_t)(threadIdx.x >> 6) * GPW + ln / CS;
-    constexpr int64_t RB = (int64_t)(BLOCK / 64) * GPW * R;
+    constexpr int64_t RBW = (int64_t)GPW * R;
+    const int64_t lane_row = (int64_t)(ln / CS) * R;
+    const int64_t wave0 = (int64_t)blockIdx.x * OWAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double acc[NCL];
 #pragma unroll
     for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
     double nrm = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
-        const int64_t r0 = base + rowgrp * R;
+    for (int64_t base = wave0 * RBW; base < ld; base += (int64_t)gridDim.x * OWAVES * RBW) {
+        const int64_t r0 = base + lane_row;
         double x[R];
         w_load(w + r0, x);
         CT ch[NCL];
@@ -386,10 +400,10 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typenam
         }
     }
     publish_split<NC, CS, NCL>(acc, nc, part, red);
-    nrm = block_sum(nrm, shd);
+    nrm = block_sum(nrm, shd, OWAVES);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_UPD], gridDim.x, &s_last)) {
-        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c2, red, shd);
+        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c2, sred, shd);
         if (threadIdx.x == 0) {
             st->wnorm2 = wn;
             int second = 1;
@@ -412,15 +426,16 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_dot(State* st, const typenam
 // two-pass modes the same pass takes the dots of the stored column with the
 // basis: the new row and column of the Gram matrix.
 template <int P, int NC, bool GRAM>
-__global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr<P>::V* __restrict__ Vb,
+__global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename Tr<P>::V* __restrict__ Vb,
                                                           const typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                           double* part, double* part2, double* gm) {
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
     __shared__ double coef[NC];
-    __shared__ double red[BLOCK / 64][NC];
+    __shared__ double red[OWAVES][NC];
     __shared__ double gcol[NC];
-    __shared__ double shd[BLOCK / 64];
+    __shared__ double shd[OWAVES];
+    __shared__ double sred[OBLOCK];
     __shared__ int s_last, s_accept;
     const int j = st->j;
     if (st->status != 0 || j >= st->m) return;
@@ -434,19 +449,20 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
     const bool second = GRAM || st->second != 0;
     constexpr bool gram = GRAM;
     const int lo = (!GRAM && st->reorth == 0 && st->mode != MODE_RESTART) ? j : 0;
-    for (int k = threadIdx.x; k < NC; k += BLOCK)
+    for (int k = threadIdx.x; k < NC; k += OBLOCK)
         coef[k] = (second && k >= lo && k < nc) ? st->c2[k] * st->scale[k] : 0.0;
     __syncthreads();
     const int ln = threadIdx.x & 63, cs = ln % CS;
-    const int64_t rowgrp = (int64_t)(threadIdx.x >> 6) * GPW + ln / CS;
-    constexpr int64_t RB = (int64_t)(BLOCK / 64) * GPW * R;
+    constexpr int64_t RBW = (int64_t)GPW * R;
+    const int64_t lane_row = (int64_t)(ln / CS) * R;
+    const int64_t wave0 = (int64_t)blockIdx.x * OWAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     auto* out = Vb + (int64_t)(j + 1) * ld;
     double nrm = 0.0;
     double acc[NCL];
 #pragma unroll
     for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * RB; base < ld; base += (int64_t)gridDim.x * RB) {
-        const int64_t r0 = base + rowgrp * R;
+    for (int64_t base = wave0 * RBW; base < ld; base += (int64_t)gridDim.x * OWAVES * RBW) {
+        const int64_t r0 = base + lane_row;
         double x[R];
         w_load(w + r0, x);
         if (second) {
@@ -484,10 +500,10 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
             for (int rr = 0; rr < R; ++rr) nrm += x[rr] * x[rr];
     }
     if (gram) publish_split<NC, CS, NCL>(acc, nc, part, red);
-    nrm = block_sum(nrm, shd);
+    nrm = block_sum(nrm, shd, OWAVES);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
     if (last_block(&st->ticket[TK_STORE], gridDim.x, &s_last)) {
-        const double tot = gram ? reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, gcol, red, shd)
+        const double tot = gram ? reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, gcol, sred, shd)
                                 : ordered_sum_dev(part2, gridDim.x, shd);
         if (threadIdx.x == 0) {
             const double b = sqrt(tot);
@@ -530,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_orth_upd_store(State* st, typename Tr
             // Gram entries of the unit stored vectors: column j+1 against 0..j
             // (gcol already carries scale_k) and its own squared norm.
             const double sn = st->scale[j + 1];
-            for (int k = threadIdx.x; k < nc; k += BLOCK) {
+            for (int k = threadIdx.x; k < nc; k += OBLOCK) {
                 const double g = gcol[k] * sn;
                 gm[k * NCMAX + (j + 1)] = g;
                 gm[(j + 1) * NCMAX + k] = g;
@@ -556,16 +572,16 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
     const int nb = nc_bucket(ncols);
 #define LZ_ORTH_CASE(NCV)                                                                                  \
     case NCV:                                                                                              \
-        hipLaunchKernelGGL((k_orth_dot<P, NCV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, w, p.ld,      \
+        hipLaunchKernelGGL((k_orth_dot<P, NCV>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w, p.ld,      \
                            b.part, b.part2, b.gm);                                                         \
         if (reorth < 2)                                                                                    \
-            hipLaunchKernelGGL((k_orth_upd_dot<P, NCV>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, w,    \
+            hipLaunchKernelGGL((k_orth_upd_dot<P, NCV>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w,    \
                                p.ld, b.part, b.part2);                                                     \
         if (reorth >= 2)                                                                                   \
-            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, true>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, V, \
+            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, true>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, \
                                w, p.ld, b.part, b.part2, b.gm);                                            \
         else                                                                                               \
-            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, false>), dim3(p.g_orth), dim3(BLOCK), 0, s, b.st,  \
+            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, false>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st,  \
                                V, w, p.ld, b.part, b.part2, b.gm);                                         \
         break;
     switch (nb) {
@@ -598,15 +614,15 @@ hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncol
 hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s) {
     switch (p.prec) {
         case 0:
-            hipLaunchKernelGGL(k_init<0>, dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, (double*)b.V, (double*)b.w, p.n,
+            hipLaunchKernelGGL(k_init<0>, dim3(p.g_dense), dim3(BLOCK), 0, s, b.st, (double*)b.V, (double*)b.w, p.n,
                                p.ld, b.part2, b.gm);
             break;
         case 1:
-            hipLaunchKernelGGL(k_init<1>, dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, (float*)b.V, (float*)b.w, p.n,
+            hipLaunchKernelGGL(k_init<1>, dim3(p.g_dense), dim3(BLOCK), 0, s, b.st, (float*)b.V, (float*)b.w, p.n,
                                p.ld, b.part2, b.gm);
             break;
         case 2:
-            hipLaunchKernelGGL(k_init<2>, dim3(p.g_orth), dim3(BLOCK), 0, s, b.st, (uint16_t*)b.V, (float*)b.w,
+            hipLaunchKernelGGL(k_init<2>, dim3(p.g_dense), dim3(BLOCK), 0, s, b.st, (uint16_t*)b.V, (float*)b.w,
                                p.n, p.ld, b.part2, b.gm);
             break;
         default:
