@@ -116,8 +116,10 @@ typedef struct lz_report {
     /* Phase timings in milliseconds (only with lz_options.profile = 1). */
     double t_setup_ms;       /* input checks, relabelling, tiles, start vector */
     double t_lanczos_ms;     /* all Lanczos iterations */
-    double t_spmv_ms;        /* mean duration of one SpMV launch */
-    double t_orth_ms;        /* mean duration of one step's reorthogonalisation */
+    double t_spmv_ms;        /* mean duration of one SpMV launch (the SpMV
+                                of every eighth step is timed) */
+    double t_orth_ms;        /* t_lanczos_ms / steps - t_spmv_ms: the rest of
+                                a step (reorthogonalisation, launch gaps) */
     double t_finish_ms;      /* Jacobi, selection, Ritz vectors, report */
     int32_t reordered;       /* 1: the solve ran on the hub-first relabelling */
     int32_t pad;

@@ -164,17 +164,24 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
     void* ws = o.workspace;
     bool owned = false;
     State* hst = nullptr;
-    hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
-    std::vector<hipEvent_t> iev;       // three per launched iteration when profiling
+    // Profiling: phase events (start, after the start vector, after the
+    // last Lanczos iteration, before and after the finish) and a pair around
+    // the SpMV of every PROFILE_STRIDE-th iteration (the SpMV does the same
+    // work at every step; each event adds a few microseconds of queue time,
+    // so the steps in between run unbracketed).
+    constexpr int PROFILE_STRIDE = 8;
+    hipEvent_t pev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> iev;       // two per sampled iteration when profiling
     int launched = m;
     auto iter_events = [&](int t) -> hipEvent_t* {
-        if (!o.profile) return nullptr;
-        while ((int)iev.size() < 3 * (t + 1)) {
+        if (!o.profile || t % PROFILE_STRIDE != 0) return nullptr;
+        const int slot = t / PROFILE_STRIDE;
+        while ((int)iev.size() < 2 * (slot + 1)) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return nullptr;
             iev.push_back(e);
         }
-        return &iev[3 * t];
+        return &iev[2 * slot];
     };
     {
         if (!ws) {
@@ -193,7 +200,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         }
         hst = pinned;
         if (o.profile) {
-            for (int i = 0; i < 4; ++i) LZ_HIP(hipEventCreate(&pev[i]));
+            for (int i = 0; i < 5; ++i) LZ_HIP(hipEventCreate(&pev[i]));
             LZ_HIP(hipEventRecord(pev[0], s));
         }
         LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, o.reorder, s));
@@ -206,6 +213,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         LZ_HIP(launch_init(p, b, s));
         if (o.profile) LZ_HIP(hipEventRecord(pev[1], s));
         for (int t = 0; t < m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, o.reorth, s, iter_events(t)));
+        if (o.profile) LZ_HIP(hipEventRecord(pev[2], s));
         // Breakdowns consume iterations without advancing j: run more until
         // m steps are done (bounded; each round advances j).
         for (int round = 0; round < 2 * LZ_MAX_STEPS + 2; ++round) {
@@ -216,14 +224,15 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             for (int t = 0; t < extra; ++t)
                 LZ_HIP(launch_iteration(p, b, a, m, o.reorth, s, iter_events(launched + t)));
             launched += extra;
+            if (o.profile) LZ_HIP(hipEventRecord(pev[2], s));
         }
         if (hst->status == 0 && hst->j < m) {
             rc = LZ_ERR_BREAKDOWN;
             goto done;
         }
-        if (o.profile) LZ_HIP(hipEventRecord(pev[2], s));
-        if (hst->status == 0) LZ_HIP(launch_finish(p, b, a, out_vals, out_vecs, o.report, s));
         if (o.profile) LZ_HIP(hipEventRecord(pev[3], s));
+        if (hst->status == 0) LZ_HIP(launch_finish(p, b, a, out_vals, out_vecs, o.report, s));
+        if (o.profile) LZ_HIP(hipEventRecord(pev[4], s));
         LZ_HIP(hipMemcpyAsync(hst, b.st, STATE_REPORT_BYTES, hipMemcpyDeviceToHost, s));
         LZ_HIP(hipStreamSynchronize(s));
         rc = hst->status;
@@ -249,18 +258,19 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             report->reordered = hst->reordered;
             if (o.profile && launched > 0) {
                 float ms = 0.f;
-                double sp = 0.0, orth = 0.0;
-                for (int t = 0; t < launched; ++t) {
-                    hipEvent_t* e = &iev[3 * t];
-                    if (hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) sp += ms;
-                    if (hipEventElapsedTime(&ms, e[1], e[2]) == hipSuccess) orth += ms;
-                }
-                report->t_spmv_ms = sp / launched;
-                report->t_orth_ms = orth / launched;
+                double sp = 0.0;
+                int ns = 0;
+                for (size_t i = 0; i + 1 < iev.size(); i += 2)
+                    if (hipEventElapsedTime(&ms, iev[i], iev[i + 1]) == hipSuccess) {
+                        sp += ms;
+                        ++ns;
+                    }
+                report->t_spmv_ms = ns ? sp / ns : 0.0;
                 if (hipEventElapsedTime(&ms, pev[0], pev[1]) == hipSuccess) report->t_setup_ms = ms;
-                if (hipEventElapsedTime(&ms, iev[0], iev[3 * launched - 1]) == hipSuccess)
-                    report->t_lanczos_ms = ms;
-                if (hipEventElapsedTime(&ms, pev[2], pev[3]) == hipSuccess) report->t_finish_ms = ms;
+                if (hipEventElapsedTime(&ms, pev[1], pev[2]) == hipSuccess) report->t_lanczos_ms = ms;
+                if (hipEventElapsedTime(&ms, pev[3], pev[4]) == hipSuccess) report->t_finish_ms = ms;
+                // The rest of a step: reorthogonalisation and launch gaps.
+                report->t_orth_ms = std::max(0.0, report->t_lanczos_ms / launched - report->t_spmv_ms);
             }
         }
     }

@@ -93,6 +93,21 @@ __device__ __forceinline__ bool last_block(uint32_t* ticket, uint32_t count, int
     return last;
 }
 
+// Sum of x[b * stride] over b = first, first + step, ... < nb, in that order
+// (device-coherent loads, issued sixteen at a time so that they are in
+// flight together).
+__device__ __forceinline__ double strided_sum_dev(const double* x, int64_t stride, int first, int step, int nb) {
+    double s = 0.0;
+    for (int b0 = first; b0 < nb; b0 += 16 * step) {
+        double v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = ld_dev(x + (int64_t)min(b0 + i * step, nb - 1) * stride);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s += b0 + i * step < nb ? v[i] : 0.0;
+    }
+    return s;
+}
+
 // Sum of x[0..cnt) (device-coherent loads) in a fixed order.
 __device__ __forceinline__ double ordered_sum_dev(const double* x, int64_t cnt, double* sh) {
     double s = 0.0;

@@ -468,7 +468,6 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
 __global__ __launch_bounds__(BLOCK) void k_resid(State* st, const double* __restrict__ Y,
                                                  const double* __restrict__ Z, int64_t n, int KB2, double* part) {
     __shared__ double shz[BLOCK];
-    __shared__ double red[4][64];
     __shared__ int s_last;
     if (st->status != 0) return;
     const int K = st->K;
@@ -502,17 +501,18 @@ __global__ __launch_bounds__(BLOCK) void k_resid(State* st, const double* __rest
         st_dev(&part[(int64_t)blockIdx.x * 64 + tid], sum);
     }
     if (last_block(&st->ticket[TK_RESID], gridDim.x, &s_last)) {
-        const int q = tid >> 6, l = tid & 63;
-        double sum = 0.0;
-        if (l < K)
-            for (int b = q; b < (int)gridDim.x; b += 4) sum += ld_dev(&part[(int64_t)b * 64 + l]);
-        red[q][l] = sum;
+        // Thread (g, k) adds workgroups g, g + groups, ... of column k; the
+        // group sums are then added in group order.
         __syncthreads();
-        if (q == 0 && l < K) {
-            const double a2 = sqrt((red[0][l] + red[1][l]) + (red[2][l] + red[3][l]));
-            const double tl = st->theta[st->sel[l]];
-            st->abs_resid[l] = a2;
-            st->resid[l] = tl != 0.0 ? a2 / fabs(tl) : a2;
+        shz[tid] = act ? strided_sum_dev(part + k, 64, g, groups, gridDim.x) : 0.0;
+        __syncthreads();
+        if (tid < K) {
+            double sum = 0.0;
+            for (int gg = 0; gg < groups; ++gg) sum += shz[gg * KB2 + tid];
+            const double a2 = sqrt(sum);
+            const double tl = st->theta[st->sel[tid]];
+            st->abs_resid[tid] = a2;
+            st->resid[tid] = tl != 0.0 ? a2 / fabs(tl) : a2;
         }
     }
 }
@@ -584,22 +584,25 @@ __global__ __launch_bounds__(BLOCK) void k_gram(const State* st, const T* __rest
     d4 acc[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    // Columns c .. 16 nb - 1 enter the MFMA tiles as zeros; only the c live
+    // columns are loaded per panel.
+    for (int idx = threadIdx.x; idx < GPR * (nb * 16 - c); idx += BLOCK) P[idx % GPR][c + idx / GPR] = 0.0;
     const int64_t npanel = (n + GPR - 1) / GPR;
     for (int64_t pn = blockIdx.x; pn < npanel; pn += gridDim.x) {
         const int64_t r0 = pn * GPR;
         __syncthreads();
-        for (int idx = threadIdx.x; idx < GPR * 64; idx += BLOCK) {
+        for (int idx = threadIdx.x; idx < GPR * c; idx += BLOCK) {
             int row, col;
             if (ROWMAJOR) {
-                row = idx >> 6;
-                col = idx & 63;
+                row = idx / c;
+                col = idx - row * c;
             } else {
                 col = idx / GPR;
                 row = idx % GPR;
             }
             const int64_t r = r0 + row;
             double v = 0.0;
-            if (col < c && r < n) v = to_d(ROWMAJOR ? X[r * ldx + col] : X[(int64_t)col * ldx + r]) * scale[col];
+            if (r < n) v = to_d(ROWMAJOR ? X[r * ldx + col] : X[(int64_t)col * ldx + r]) * scale[col];
             P[row][col] = v;
         }
         __syncthreads();

@@ -134,8 +134,7 @@ hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s);
 // One Lanczos iteration (SpMV or restart draw, reorthogonalisation, store);
 // `reorth` is the solve's LZ_REORTH_* mode (it selects the kernels).
 // `ncols_bound` >= j+1 for every j the iteration can see.
-// With `ev` non-null, ev[0] is recorded before the SpMV, ev[1] after it and
-// ev[2] after the reorthogonalisation kernels.
+// With `ev` non-null, ev[0] is recorded before the SpMV and ev[1] after it.
 hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols_bound, int reorth,
                             hipStream_t s, hipEvent_t* ev = nullptr);
 // The Lanczos-step SpMV of the current iteration (or its restart draw).

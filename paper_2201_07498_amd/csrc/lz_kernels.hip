@@ -597,7 +597,6 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
             return hipErrorInvalidValue;
     }
 #undef LZ_ORTH_CASE
-    if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 

@@ -272,6 +272,24 @@ def test_reorth_modes_run(reorth):
     assert eig_rel_err(vals, ref["vals"]) <= 1e-9
 
 
+def test_profiled_solve_matches_unprofiled_and_fills_timings():
+    # Events only observe the stream: results are bitwise those of a solve
+    # without them, and the phase times are positive and consistent.
+    rp, c, v = synth.rmat(13, 8, seed=4)
+    K, m = 6, 20
+    drp, dc, dv = device_csr(rp, c, v, "fp32")
+    a = lz.topk(drp, dc, dv, K, m, "fp32", seed=9)
+    b = lz.topk(drp, dc, dv, K, m, "fp32", seed=9, profile=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    r = b[2]
+    for key in ("t_setup_ms", "t_lanczos_ms", "t_spmv_ms", "t_finish_ms"):
+        assert r[key] > 0.0, key
+    assert r["t_orth_ms"] >= 0.0
+    assert m * r["t_spmv_ms"] <= r["t_lanczos_ms"] * 1.05
+    assert a[2]["t_lanczos_ms"] == 0.0
+
+
 def test_plain_entry_point_matches_ex():
     rp, c, v = synth.er(3000, 9.0, seed=0)
     drp, dc, dv = device_csr(rp, c, v, "fp64")
