@@ -339,31 +339,36 @@ __global__ __launch_bounds__(BLOCK) void k_colstats(State* st, const double* __r
 
 // Residual check (Sec. IV-D) in FP64 for all K Ritz pairs at once.
 // First Z = A Y (stored matrix values upcast exactly) over the SpMV tiles:
-// each wavefront stages its tile's col/val in LDS; lane k of a group of KB2
+// each wavefront stages its tile's col/val in LDS (values in the storage
+// precision, upcast when used); lane k of a group of KB2
 // lanes owns pair k and gathers K-wide rows of Y.  Rows are spread over the
 // 64/KB2 groups; a row longer than LONGZ, and a split row's piece, is shared
 // by all groups.  Split rows are finished by their last piece as in the
 // SpMV, the pieces added in tile order.
 constexpr int LONGZ = 32;
 
-// sum over p = p0, p0+step, ... < e of sval[p] * Y[scol[p]][k], with four
-// gathers in flight per lane (fixed association order).
-__device__ __forceinline__ double gather_dot(const int* scol, const double* sval, int p0, int e, int step,
+// sum over p = p0, p0+step, ... < e of sval[p] * Y[scol[p]][k].  Eight
+// gathers per lane are issued together, those past the end clamped to the
+// batch's first entry and discarded, so a row of up to eight entries costs
+// one round of requests; fixed association order.
+template <class VT>
+__device__ __forceinline__ double gather_dot(const int* scol, const VT* sval, int p0, int e, int step,
                                              const double* __restrict__ Y, int K, int k) {
-    double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-    int p = p0;
-    for (; p + 3 * step < e; p += 4 * step) {
-        const double y0 = Y[(int64_t)scol[p] * K + k];
-        const double y1 = Y[(int64_t)scol[p + step] * K + k];
-        const double y2 = Y[(int64_t)scol[p + 2 * step] * K + k];
-        const double y3 = Y[(int64_t)scol[p + 3 * step] * K + k];
-        z0 += sval[p] * y0;
-        z1 += sval[p + step] * y1;
-        z2 += sval[p + 2 * step] * y2;
-        z3 += sval[p + 3 * step] * y3;
+    double z[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int p = p0; p < e; p += 8 * step) {
+        double y[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int q = p + i * step < e ? p + i * step : p;
+            y[i] = Y[(int64_t)scol[q] * K + k];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int q = p + i * step;
+            z[i] += q < e ? to_d(sval[q]) * y[i] : 0.0;
+        }
     }
-    for (; p < e; p += step) z0 += sval[p] * Y[(int64_t)scol[p] * K + k];
-    return (z0 + z1) + (z2 + z3);
+    return ((z[0] + z[1]) + (z[2] + z[3])) + ((z[4] + z[5]) + (z[6] + z[7]));
 }
 
 // Adds the groups' values (lanes that differ in the group bits), fixed order.
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
                                                 uint32_t* tk, double* head, double* tail, int KB2) {
     using VT = typename Tr<P>::V;
     __shared__ int scol_all[WAVES][TILE];
-    __shared__ double sval_all[WAVES][TILE];
+    __shared__ VT sval_all[WAVES][TILE];
     if (st->status != 0) return;
     const int64_t* rp = st->crp;
     const int32_t* col = st->ccol;
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
     const int G = 64 / KB2, g = lane / KB2, k = lane % KB2;
     const bool act = k < K;
     int* scol = scol_all[threadIdx.x >> 6];
-    double* sval = sval_all[threadIdx.x >> 6];
+    VT* sval = sval_all[threadIdx.x >> 6];
     // Pieces of split row r (tail pieces in t1..t2-1, head piece in t2),
     // added group-strided in tile order; the whole row sum in every group.
     auto split_total_k = [&](int64_t t1, int64_t t2) {
@@ -405,7 +410,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
         const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
         for (int i = lane; i < cnt; i += 64) {
             scol[i] = col[t0 + i];
-            sval[i] = to_d(val[t0 + i]);
+            sval[i] = val[t0 + i];
         }
         wave_sync();
         const bool split_head = r_lo < r_hi && rp[r_lo] < t0;

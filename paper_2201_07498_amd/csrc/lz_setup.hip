@@ -260,40 +260,67 @@ __global__ __launch_bounds__(BLOCK) void k_rl_rowlen(const State* st, const int6
 }
 
 // Copies every row to its new place, columns relabelled.  One wavefront per
-// SpMV tile of the relabelled matrix (balanced over entries and rows): the
-// tile's row pointers are staged in LDS and each entry finds its row there.
+// SpMV tile of the relabelled matrix (balanced over entries and rows).  The
+// tile's rows are staged in LDS once: their first new position rp2 and the
+// shift from new to old position (rp[perm[row]] - rp2[row]).  Each lane then
+// takes its 16 entries together: a fixed-step search over the staged rows,
+// then all 16 col/val loads, then all 16 iperm gathers, so a tile costs two
+// rounds of requests.
+constexpr int FILL_WAVES = 2;
 template <class VT>
-__global__ __launch_bounds__(BLOCK) void k_rl_fill(const State* st, const int64_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                                   int64_t n, int64_t nnz, int64_t n_tiles,
-                                                   const int32_t* __restrict__ ob, const int32_t* __restrict__ perm,
-                                                   const int32_t* __restrict__ iperm, const int64_t* __restrict__ rp2,
-                                                   int32_t* __restrict__ col2, VT* __restrict__ val2) {
-    __shared__ int64_t srp[WAVES][TILE + 2];
+__global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, const int64_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            const VT* __restrict__ val, int64_t n, int64_t nnz,
+                                                            int64_t n_tiles, const int32_t* __restrict__ ob,
+                                                            const int32_t* __restrict__ perm,
+                                                            const int32_t* __restrict__ iperm,
+                                                            const int64_t* __restrict__ rp2,
+                                                            int32_t* __restrict__ col2, VT* __restrict__ val2) {
+    __shared__ int64_t srp[FILL_WAVES][TILE + 2];
+    __shared__ int64_t sdel[FILL_WAVES][TILE + 1];
     if (!st->reordered) return;
     const int lane = threadIdx.x & 63;
     int64_t* s = srp[threadIdx.x >> 6];
-    const TileRange tr = wave_tiles(n_tiles);
+    int64_t* d = sdel[threadIdx.x >> 6];
+    const TileRange tr = wave_tiles<FILL_WAVES>(n_tiles);
     for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
         const int64_t r_lo = ob[t], r_hi = ob[t + 1];
         const int64_t t0 = t * TILE - r_lo;
         const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
-        // Rows r_lo .. r_last touch the tile; stage rp2[r_lo .. r_last + 1].
+        if (cnt <= 0) continue;                   // row ends only: no entries to move
+        // Rows r_lo .. r_last touch the tile (at most TILE + 1 of them).
         const int64_t r_last = min(r_hi, n - 1);
-        const int nrp = (int)(r_last - r_lo + 2);
-        for (int i = lane; i < nrp; i += 64) s[i] = rp2[r_lo + i];
+        const int nr = (int)(r_last - r_lo + 1);
+        for (int i = lane; i <= nr; i += 64) s[i] = rp2[r_lo + i];
+        for (int i = lane; i < nr; i += 64) d[i] = rp[perm[r_lo + i]] - rp2[r_lo + i];
         wave_sync();
-        for (int k = lane; k < cnt; k += 64) {
-            const int64_t q = t0 + k;
-            // Largest i with s[i] <= q (that row's range holds q).
-            int lo = 0, hi = nrp - 2;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s[mid] <= q) lo = mid; else hi = mid - 1;
+        int64_t src[TP];
+#pragma unroll
+        for (int e = 0; e < TP; ++e) {
+            const int64_t q = t0 + min(e * 64 + lane, cnt - 1);
+            // Largest i < nr with s[i] <= q (the row whose range holds q).
+            int lo = 0;
+#pragma unroll
+            for (int step = TILE; step > 0; step >>= 1)
+                if (lo + step < nr && s[lo + step] <= q) lo += step;
+            src[e] = q + d[lo];
+        }
+        int32_t c[TP];
+        VT v[TP];
+#pragma unroll
+        for (int e = 0; e < TP; ++e) {
+            c[e] = col[src[e]];
+            v[e] = val[src[e]];
+        }
+#pragma unroll
+        for (int e = 0; e < TP; ++e) c[e] = iperm[c[e]];
+#pragma unroll
+        for (int e = 0; e < TP; ++e) {
+            const int k = e * 64 + lane;
+            if (k < cnt) {
+                col2[t0 + k] = c[e];
+                val2[t0 + k] = v[e];
             }
-            const int64_t src = rp[perm[r_lo + lo]] + (q - s[lo]);
-            col2[q] = iperm[col[src]];
-            val2[q] = val[src];
         }
         wave_sync();
     }
@@ -351,17 +378,17 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
     if (reorder != LZ_REORDER_OFF) {
         switch (p.prec) {
             case 0:
-                hipLaunchKernelGGL(k_rl_fill<double>, dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                hipLaunchKernelGGL(k_rl_fill<double>, dim3(p.g_tile * (WAVES / FILL_WAVES)), dim3(FILL_WAVES * 64), 0, s, b.st, a.rowptr, a.col,
                                    (const double*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
                                    (double*)b.val2);
                 break;
             case 1:
-                hipLaunchKernelGGL(k_rl_fill<float>, dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                hipLaunchKernelGGL(k_rl_fill<float>, dim3(p.g_tile * (WAVES / FILL_WAVES)), dim3(FILL_WAVES * 64), 0, s, b.st, a.rowptr, a.col,
                                    (const float*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
                                    (float*)b.val2);
                 break;
             default:
-                hipLaunchKernelGGL(k_rl_fill<uint16_t>, dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                hipLaunchKernelGGL(k_rl_fill<uint16_t>, dim3(p.g_tile * (WAVES / FILL_WAVES)), dim3(FILL_WAVES * 64), 0, s, b.st, a.rowptr, a.col,
                                    (const uint16_t*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
                                    (uint16_t*)b.val2);
                 break;
