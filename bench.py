@@ -36,7 +36,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SpMV HBM GB/s + Top-K solves/sec, p50/p99 latency at eigval rel err ≤1e-6"
 HBM_PEAK_GBPS = 8000.0
-BYTES = {"fp64": (8, 8), "fp32": (4, 4), "bf16": (2, 4)}   # (stored value/vector bytes, working-vector bytes)
+BYTES = {"fp64": (8, 8), "fp32": (4, 4), "bf16": (2, 4),   # (stored value/vector bytes, working-vector bytes)
+         "fp32-fff": (4, 4)}
+
+
+def mode_of(p: str):
+    """Bench mode -> (storage precision, arithmetic).  "fp32-fff" is FP32
+    storage with all-FP32 arithmetic (dots, norms, reorthogonalisation)."""
+    return ("fp32", "fp32") if p == "fp32-fff" else (p, "mixed")
 
 
 def workload(name: str):
@@ -45,7 +52,7 @@ def workload(name: str):
         rp, c, v = synth.rmat(20, 8, seed=0)
         v = synth.normalize_sym(rp, c, synth.round_values(v, "fp32"))
         v = synth.round_values(v, "fp32")
-        return dict(rp=rp, col=c, val=v, K=16, m=48, precisions=("fp32", "fp64"),
+        return dict(rp=rp, col=c, val=v, K=16, m=48, precisions=("fp32", "fp64", "fp32-fff"),
                     desc="R-MAT scale 20, edge factor 8, (0.57,0.19,0.19,0.05), symmetrised, "
                          "D^-1/2 A D^-1/2, FP32-rounded values")
     if name == "er10k":
@@ -104,20 +111,22 @@ def measured_traffic(workload: str, precision: str):
         return None
 
 
-def run_mode(lz, dev_csr, K, m, precision, steps, warmup, ws):
+def run_mode(lz, dev_csr, K, m, mode, steps, warmup, ws):
     import torch
     rp, col, val = dev_csr
+    precision, arith = mode_of(mode)
     n = rp.numel() - 1
     out = (torch.empty(K, dtype=torch.float64, device=rp.device),
            torch.empty(K, n, dtype=torch.float64, device=rp.device))
     for _ in range(warmup):
-        lz.topk(rp, col, val, K, m, precision, seed=0, workspace=ws, out=out, profile=True)
+        lz.topk(rp, col, val, K, m, precision, seed=0, workspace=ws, out=out, profile=True, arith=arith)
     torch.cuda.synchronize()
     lat, reps = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
-        vals, vecs, rep = lz.topk(rp, col, val, K, m, precision, seed=0, workspace=ws, out=out, profile=True)
+        vals, vecs, rep = lz.topk(rp, col, val, K, m, precision, seed=0, workspace=ws, out=out, profile=True,
+                                  arith=arith)
         lat.append(time.perf_counter() - ts)
         reps.append(rep)
     torch.cuda.synchronize()
@@ -260,6 +269,58 @@ def serving_main(args):
     print(json.dumps(line), flush=True)
 
 
+def study_reorth(args, W, lz, torch, device_csr, eig_rel_err):
+    """Sec. IV-D accuracy measures (orthogonality of the basis and of the Ritz
+    vectors, mean pairwise angle, residuals) and solve time for each
+    reorthogonalisation mode, per storage precision and K (m = 3K).  The
+    eigenvalue error is against the FP64 two-pass run of the same K."""
+    rp, col, val = W["rp"], W["col"], W["val"]
+    n, nnz = rp.size - 1, int(rp[-1])
+    precs = tuple(dict.fromkeys(("fp64",) + tuple(W["precisions"])))
+    ks = (8, 16, 32)
+    ws = torch.empty(max(lz.workspace_size(n, nnz, 32, 64, mode_of(p)[0]) for p in precs),
+                     dtype=torch.uint8, device="cuda:0")
+    rows, ref = [], {}
+    for p in precs:
+        prec, arith = mode_of(p)
+        dcsr = device_csr(rp, col, val, prec, torch.device("cuda:0"))
+        for K in ks:
+            m = min(3 * K, 64)
+            out = (torch.empty(K, dtype=torch.float64, device="cuda:0"),
+                   torch.empty(K, n, dtype=torch.float64, device="cuda:0"))
+            for mode in ("twice", "selective", "once", "none"):
+                try:
+                    lz.topk(*dcsr, K, m, prec, seed=0, reorth=mode, workspace=ws, out=out, arith=arith)
+                except lz.LanczosError as e:       # e.g. no convergence without reorthogonalisation
+                    torch.cuda.synchronize()
+                    rows.append({"precision": p, "reorth": mode, "K": K, "m": m, "error": str(e)})
+                    print(f"[study] {p} {mode} K={K}: {e}", file=sys.stderr, flush=True)
+                    continue
+                torch.cuda.synchronize()
+                reps = max(1, min(args.steps, 5))
+                t = time.perf_counter()
+                for _ in range(reps):
+                    vals, _, rep = lz.topk(*dcsr, K, m, prec, seed=0, reorth=mode, workspace=ws, out=out, arith=arith)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t) / reps
+                v = vals.cpu().numpy()
+                if p == "fp64" and mode == "twice":
+                    ref[K] = v
+                row = {"precision": p, "reorth": mode, "K": K, "m": m, "ms_per_solve": dt * 1e3,
+                       "status": rep["status"], "restarts": rep["restarts"],
+                       "ortho_loss": rep["ortho_loss"], "ritz_ortho_loss": rep["ritz_ortho_loss"],
+                       "mean_angle_deg": rep["mean_angle_deg"], "resid_max": float(np.max(rep["resid"])),
+                       "resid_median": float(np.median(rep["resid"])),
+                       "eig_rel_err_vs_fp64_twice": eig_rel_err(v, ref[K]) if K in ref else None}
+                rows.append(row)
+                print(f"[study] {p} {mode:9s} K={K:2d} m={m:2d}: {dt * 1e3:7.2f} ms  ortho {row['ortho_loss']:.1e}"
+                      f"  ritz ortho {row['ritz_ortho_loss']:.1e}  angle {row['mean_angle_deg']:.3f}"
+                      f"  resid max {row['resid_max']:.1e}  eig err {row['eig_rel_err_vs_fp64_twice']}",
+                      file=sys.stderr, flush=True)
+        del dcsr
+    print(json.dumps({"study": "reorth", "workload": args.workload, "n": n, "nnz": nnz, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +338,9 @@ def main():
                     help="first run a plain copy kernel (1 GiB read + 1 GiB written, three launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic of the other kernels")
     ap.add_argument("--precisions", default=None, help="comma list overriding the workload's precisions")
+    ap.add_argument("--study", default=None, choices=["reorth"],
+                    help="reorth: accuracy and time of the reorthogonalisation modes (none/once/twice/"
+                         "selective) for K in {8, 16, 32}, m = 3K, on the workload; prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -307,12 +371,14 @@ def main():
     print(f"[bench] workload {args.workload}: n={n} nnz={nnz} K={K} m={m} (gen {time.perf_counter() - t:.1f}s)",
           file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
-    ws_bytes = max(lz.workspace_size(n, nnz, K, m, p) for p in W["precisions"])
+    if args.study == "reorth":
+        return study_reorth(args, W, lz, torch, device_csr, eig_rel_err)
+    ws_bytes = max(lz.workspace_size(n, nnz, K, m, mode_of(p)[0]) for p in W["precisions"])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
     results = {}
     for p in W["precisions"]:
-        dcsr = device_csr(rp, col, val, p, dev)
+        dcsr = device_csr(rp, col, val, mode_of(p)[0], dev)
         torch.cuda.synchronize()
         r = run_mode(lz, dcsr, K, m, p, args.steps, args.warmup, ws)
         t_spmv = float(np.mean([x["t_spmv_ms"] for x in r["reps"]]))
@@ -342,7 +408,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[head],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "fp32-fff": "f32"}[head],
         "data": "synthetic",
         "config": {"workload": args.workload, "description": W["desc"], "n": n, "nnz": nnz, "K": K, "m": m,
                    "precision": head, "reorth": "twice", "parallelism": "single-gpu"},
@@ -370,6 +436,8 @@ def main():
                    "phases_ms": {"lanczos": r["t_lanczos_ms"], "spmv_per_step": r["t_spmv_ms"],
                                  "orth_per_step": r["t_orth_ms"], "finish": r["t_finish_ms"]}}
         line[f"speedup_{head}_vs_{p}"] = line["value"] / line[p]["solves_per_s"]
+        if p != "fp64" and "fp64" in results:
+            line[p]["eig_rel_err_vs_fp64_gpu"] = eig_rel_err(r["vals"], results["fp64"]["vals"])
 
     line["roofline"]["traffic"] = measured_traffic(args.workload, head)
     if "fp64" in results and head != "fp64":

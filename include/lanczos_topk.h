@@ -79,6 +79,20 @@ typedef enum {
                                   holds at least 32 times the mean row
                                   length (power-law graphs); default */
 
+/* Arithmetic of the FP32 storage mode (Sec. III-A keeps the intermediate
+   operations of every kernel in double while vectors are stored in float;
+   Sec. IV-D compares that with all-double and all-float runs).  Jacobi, the
+   Ritz vectors and the report are FP64 in every mode. */
+#define LZ_ARITH_MIXED 0       /* dots, norms and reorthogonalisation in FP64,
+                                  SpMV accumulation in the storage's working
+                                  precision; default */
+#define LZ_ARITH_FP32 1        /* all-float: dots, norms, reorthogonalisation,
+                                  the Gram correction, alpha, beta and the SpMV
+                                  epilogue in FP32 (the start vector's norm is
+                                  summed in FP64, its scale rounded to FP32);
+                                  LZ_FP32 storage only, else
+                                  LZ_ERR_INVALID_ARG */
+
 typedef struct lz_options {
     uint64_t seed;           /* start vector: u_r = U01(SplitMix64(seed, r)),
                                 v_1 = u/||u||; default 0 */
@@ -90,6 +104,7 @@ typedef struct lz_options {
     int32_t profile;         /* 1: time the phases with HIP events recorded
                                 on `stream` (fills the t_* report fields) */
     int32_t reorder;         /* LZ_REORDER_*; default LZ_REORDER_AUTO */
+    int32_t arith;           /* LZ_ARITH_*; default LZ_ARITH_MIXED */
 } lz_options;
 
 /* Results of one solve, filled on the host when the call returns. */

@@ -19,6 +19,7 @@ LZ_FP64, LZ_FP32, LZ_BF16 = 0, 1, 2
 PRECISION = {"fp64": LZ_FP64, "fp32": LZ_FP32, "bf16": LZ_BF16}
 REORTH = {"none": 0, "once": 1, "twice": 2, "selective": 3}
 REORDER = {"off": 0, "hubs": 1, "auto": 2}
+ARITH = {"mixed": 0, "fp32": 1}
 MAX_STEPS = 64
 STATUS = {0: "LZ_OK", -1: "LZ_ERR_INVALID_ARG", -2: "LZ_ERR_OUT_OF_MEMORY", -3: "LZ_ERR_HIP",
           -4: "LZ_ERR_WORKSPACE_TOO_SMALL", -5: "LZ_ERR_TOO_LARGE", -6: "LZ_ERR_NOT_CONVERGED",
@@ -34,7 +35,7 @@ class LanczosError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("reorth", ctypes.c_int32), ("report", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("profile", ctypes.c_int32), ("reorder", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("reorder", ctypes.c_int32), ("arith", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -120,7 +121,7 @@ def workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
 
 def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
          report: bool = True, stream=None, workspace=None, nnz: int | None = None,
-         profile: bool = False, out=None, reorder="auto"):
+         profile: bool = False, out=None, reorder="auto", arith="mixed"):
     """Top-K eigenpairs.  Returns (vals[K], vecs[n, K] view of the column-major
     output, report dict)."""
     import torch
@@ -142,6 +143,7 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
     opt.report = 1 if report else 0
     opt.profile = 1 if profile else 0
     opt.reorder = REORDER[reorder] if isinstance(reorder, str) else int(reorder)
+    opt.arith = ARITH[arith] if isinstance(arith, str) else int(arith)
     if workspace is not None:
         opt.workspace = ctypes.c_void_p(workspace.data_ptr())
         opt.workspace_bytes = workspace.numel() * workspace.element_size()

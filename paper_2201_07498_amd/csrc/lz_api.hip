@@ -157,7 +157,10 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
     if (opt) o = *opt;
     if (o.reorth < LZ_REORTH_NONE || o.reorth > LZ_REORTH_SELECTIVE) return LZ_ERR_INVALID_ARG;
     if (o.reorder < LZ_REORDER_OFF || o.reorder > LZ_REORDER_AUTO) return LZ_ERR_INVALID_ARG;
+    if (o.arith < LZ_ARITH_MIXED || o.arith > LZ_ARITH_FP32) return LZ_ERR_INVALID_ARG;
+    if (o.arith == LZ_ARITH_FP32 && precision != LZ_FP32) return LZ_ERR_INVALID_ARG;
     Plan p = make_plan(n, nnz, K, m, precision);
+    p.fff = o.arith == LZ_ARITH_FP32;
     if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
 
     hipStream_t s = (hipStream_t)stream;

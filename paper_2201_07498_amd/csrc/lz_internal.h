@@ -36,7 +36,8 @@ struct State {
     int32_t restarts;
     int32_t status;       // lz_status
     int32_t m, K, reorth, second;   // `second`: run the second update of this step
-    int32_t n_items, n_long, sweeps, pad0;
+    int32_t n_items, n_long, sweeps;
+    int32_t arith;        // LZ_ARITH_FP32: dots, norms, reorthogonalisation and SpMV epilogue in FP32
     uint32_t ticket[TK_COUNT];
     uint64_t seed;
     double u_s;           // unit roundoff of the stored basis (selective reorthogonalisation)
@@ -76,6 +77,7 @@ struct Plan {
     int32_t K = 0, m = 0, prec = 0, KB = 0;
     int32_t g_orth = 0, g_dense = 0, g_tile = 0;
     int32_t xcache = 0;         // Lanczos-step SpMV keeps the head of x in LDS (set once the row order is known)
+    int32_t fff = 0;            // all-FP32 arithmetic (FP32 storage only): float instantiations
     int64_t n_tiles = 0;
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
            off_Y = 0, off_Z = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0, off_tail = 0, off_rp2 = 0,

@@ -55,8 +55,14 @@ __global__ __launch_bounds__(BLOCK) void k_init(State* st, typename Tr<P>::V* V,
     if (last_block(&st->ticket[TK_INIT], gridDim.x, &s_last)) {
         const double tot = ordered_sum_dev(part, gridDim.x, sh);
         if (threadIdx.x == 0) {
-            st->scale[0] = 1.0 / sqrt(tot);
-            gm[0] = tot * st->scale[0] * st->scale[0];
+            if (st->arith) {               // all-FP32 mode: the norm's square root and scale in FP32
+                const float sc = 1.0f / sqrtf((float)tot);
+                st->scale[0] = sc;
+                gm[0] = (double)((float)tot * sc * sc);
+            } else {
+                st->scale[0] = 1.0 / sqrt(tot);
+                gm[0] = tot * st->scale[0] * st->scale[0];
+            }
             st->beta[0] = 0.0;
             st->j = 0;
             st->mode = MODE_NORMAL;
@@ -100,7 +106,8 @@ __device__ __forceinline__ void opaque(float4& c) { asm volatile("" : "+v"(c.x),
 __device__ __forceinline__ void opaque(uint4& c) { asm volatile("" : "+v"(c.x), "+v"(c.y), "+v"(c.z), "+v"(c.w)); }
 
 __device__ __forceinline__ void unpack(const double2& c, double (&o)[2]) { o[0] = c.x; o[1] = c.y; }
-__device__ __forceinline__ void unpack(const float4& c, double (&o)[4]) {
+template <class A>
+__device__ __forceinline__ void unpack(const float4& c, A (&o)[4]) {
     o[0] = c.x; o[1] = c.y; o[2] = c.z; o[3] = c.w;
 }
 __device__ __forceinline__ double bf_lo(uint32_t u) { return (double)__uint_as_float(u << 16); }
@@ -112,7 +119,8 @@ __device__ __forceinline__ void unpack(const uint4& c, double (&o)[8]) {
 
 // R rows of the working vector w.
 __device__ __forceinline__ void w_load(const double* w, double (&o)[2]) { unpack(*(const double2*)w, o); }
-__device__ __forceinline__ void w_load(const float* w, double (&o)[4]) { unpack(*(const float4*)w, o); }
+template <class A>
+__device__ __forceinline__ void w_load(const float* w, A (&o)[4]) { unpack(*(const float4*)w, o); }
 __device__ __forceinline__ void w_load(const float* w, double (&o)[8]) {
     const float4 a = *(const float4*)w, b = *((const float4*)w + 1);
     o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w; o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
@@ -121,7 +129,8 @@ __device__ __forceinline__ void w_load(const float* w, double (&o)[8]) {
 __device__ __forceinline__ void w_round_store(double* w, double (&x)[2], bool st) {
     if (st) *(double2*)w = make_double2(x[0], x[1]);
 }
-__device__ __forceinline__ void w_round_store(float* w, double (&x)[4], bool st) {
+template <class A>
+__device__ __forceinline__ void w_round_store(float* w, A (&x)[4], bool st) {
     const float4 a = make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
     x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
     if (st) *(float4*)w = a;
@@ -137,7 +146,8 @@ __device__ __forceinline__ void w_round_store(float* w, double (&x)[8], bool st)
 }
 // Round x to the basis precision in place; store when `st` is set.
 __device__ __forceinline__ void v_round_store(double* v, double (&x)[2], bool st) { w_round_store(v, x, st); }
-__device__ __forceinline__ void v_round_store(float* v, double (&x)[4], bool st) { w_round_store(v, x, st); }
+template <class A>
+__device__ __forceinline__ void v_round_store(float* v, A (&x)[4], bool st) { w_round_store(v, x, st); }
 __device__ __forceinline__ void v_round_store(uint16_t* v, double (&x)[8], bool st) {
     uint32_t h[8];
 #pragma unroll
@@ -158,22 +168,22 @@ constexpr int OWAVES = OBLOCK / 64;
 // equal); lanes 0..CS-1 write them to red[wave][column].  Then thread k < nc
 // publishes the workgroup sum of column k (wavefronts in order) to
 // part[blockIdx.x*NCMAX + k].
-template <int NC, int CS, int NCL>
-__device__ __forceinline__ void publish_split(const double (&acc)[NCL], int nc, double* part, double (*red)[NC]) {
+template <int NC, int CS, int NCL, class A>
+__device__ __forceinline__ void publish_split(const A (&acc)[NCL], int nc, double* part, A (*red)[NC]) {
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, cs = ln % CS;
 #pragma unroll
     for (int kk = 0; kk < NCL; ++kk) {
-        double v = acc[kk];
+        A v = acc[kk];
 #pragma unroll
         for (int o = CS; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
         if (ln < CS) red[wv][cs * NCL + kk] = v;
     }
     __syncthreads();
     if ((int)threadIdx.x < nc) {
-        double s = red[0][threadIdx.x];
+        A s = red[0][threadIdx.x];
 #pragma unroll
         for (int q = 1; q < OWAVES; ++q) s += red[q][threadIdx.x];
-        st_dev(&part[(int64_t)blockIdx.x * NCMAX + threadIdx.x], s);
+        st_dev(&part[(int64_t)blockIdx.x * NCMAX + threadIdx.x], (double)s);
     }
 }
 
@@ -184,9 +194,9 @@ __device__ __forceinline__ void publish_split(const double (&acc)[NCL], int nc, 
 // on one another and are all issued before the first add, so the workgroup
 // waits for one round of loads.  The S slice sums of a column are then added
 // in slice order: the result depends on nb only, not on scheduling.
-template <int NC>
-__device__ __forceinline__ double reduce_columns(const double* part, const double* p2, int nb, int nc,
-                                                 const double* mul, double* out, double* sred, double* sh) {
+template <int NC, class A>
+__device__ __forceinline__ A reduce_columns(const double* part, const double* p2, int nb, int nc,
+                                            const double* mul, double* out, A* sred, A* sh) {
     constexpr int NCC = NC + 1, S = OBLOCK / NCC, RPT = (OGRID + S - 1) / S;
     static_assert(NC <= NCMAX && S >= 1, "column count");
     const int t = threadIdx.x, col = t % NCC, slice = t / NCC;
@@ -196,36 +206,38 @@ __device__ __forceinline__ double reduce_columns(const double* part, const doubl
         double v[RPT];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) v[i] = ld_dev(src + (int64_t)min(slice + i * S, nb - 1) * stride);
-        double s = 0.0;
+        A s = A(0);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) s += slice + i * S < nb ? v[i] : 0.0;
+        for (int i = 0; i < RPT; ++i) s += slice + i * S < nb ? (A)v[i] : A(0);
         sred[t] = s;
     }
     __syncthreads();
     if (t < NCC) {
-        double s = sred[t];
+        A s = sred[t];
         for (int q = 1; q < S; ++q) s += sred[q * NCC + t];
-        if (t < nc) out[t] = mul[t] * s;
+        if (t < nc) out[t] = (double)((A)mul[t] * s);
         if (t == NC) sh[0] = s;
     }
     __syncthreads();
-    const double tot = sh[0];
+    const A tot = sh[0];
     __syncthreads();
     return tot;
 }
 
 // c = V[:,0..j]^T w (coefficients with respect to the unit basis vectors).
-template <int P, int NC>
+// A is the arithmetic of the dots, norms and update: double, or float in the
+// all-FP32 mode.
+template <int P, int NC, class A>
 __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                     const typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                     double* part, double* part2, const double* __restrict__ gm) {
     using VT = typename Tr<P>::V;
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
-    __shared__ double red[OWAVES][NC];
-    __shared__ double sc[NC];
-    __shared__ double shd[OWAVES];
-    __shared__ double sred[OBLOCK];
+    __shared__ A red[OWAVES][NC];
+    __shared__ A sc[NC];
+    __shared__ A shd[OWAVES];
+    __shared__ A sred[OBLOCK];
     __shared__ int s_last;
     const int j = st->j;
     if (st->status != 0 || j >= st->m || !dot_active(st)) return;
@@ -238,13 +250,13 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
     constexpr int64_t RBW = (int64_t)GPW * R;
     const int64_t lane_row = (int64_t)(ln / CS) * R;
     const int64_t wave0 = (int64_t)blockIdx.x * OWAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double acc[NCL];
+    A acc[NCL];
 #pragma unroll
-    for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
-    double nrm = 0.0;
+    for (int kk = 0; kk < NCL; ++kk) acc[kk] = A(0);
+    A nrm = A(0);
     for (int64_t base = wave0 * RBW; base < ld; base += (int64_t)gridDim.x * OWAVES * RBW) {
         const int64_t r0 = base + lane_row;
-        double x[R];
+        A x[R];
         w_load(w + r0, x);
         if (cs == 0)
 #pragma unroll
@@ -259,9 +271,9 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
         for (int kk = 0; kk < NCL; ++kk) {
             const int k = cs * NCL + kk;
             if (k < nc) {
-                double v[R];
+                A v[R];
                 unpack(ch[kk], v);
-                double s = 0.0;
+                A s = A(0);
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) s += v[rr] * x[rr];
                 acc[kk] += s;
@@ -270,40 +282,40 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
     }
     publish_split<NC, CS, NCL>(acc, nc, part, red);
     nrm = block_sum(nrm, shd, OWAVES);
-    if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
+    if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], (double)nrm);
     if (last_block(&st->ticket[TK_DOT], gridDim.x, &s_last)) {
-        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c, sred, shd);
+        const A wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c, sred, shd);
         if (gram_mode(st)) {
             // Second coefficients of classical Gram-Schmidt without a second
             // pass: V^T (w - V c) = c - G c, G the Gram matrix of the unit
             // stored basis.  The update then subtracts V (c + c2) at once, in
-            // FP64 registers, so no rounded intermediate w' exists.
-            for (int k = threadIdx.x; k < nc; k += OBLOCK) sc[k] = st->c[k];
+            // registers, so no rounded intermediate w' exists.
+            for (int k = threadIdx.x; k < nc; k += OBLOCK) sc[k] = (A)st->c[k];
             __syncthreads();
-            double c2 = 0.0;
+            A c2 = A(0);
             if ((int)threadIdx.x < nc) {
-                double gc = 0.0;
-                for (int l = 0; l < nc; ++l) gc += gm[threadIdx.x * NCMAX + l] * sc[l];
+                A gc = A(0);
+                for (int l = 0; l < nc; ++l) gc += (A)gm[threadIdx.x * NCMAX + l] * sc[l];
                 c2 = sc[threadIdx.x] - gc;
             }
             // Selective: skip the correction when it is below the rounding of
             // the stored vector, ||c2|| <= u_s ||w - V c||, with
             // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c).
-            double sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : 0.0,
-                             (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : 0.0,
-                             (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : 0.0};
+            A sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : A(0),
+                        (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : A(0),
+                        (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : A(0)};
             for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
-            const double w1 = fmax(0.0, wn - 2.0 * sel[1] + sel[2]);
-            const bool corr = st->reorth == 2 || st->mode == MODE_RESTART || sel[0] > st->u_s * st->u_s * w1;
-            if ((int)threadIdx.x < nc) st->c2[threadIdx.x] = sc[threadIdx.x] + (corr ? c2 : 0.0);
+            const A w1 = fmax(A(0), wn - A(2) * sel[1] + sel[2]);
+            const bool corr = st->reorth == 2 || st->mode == MODE_RESTART || sel[0] > (A)(st->u_s * st->u_s) * w1;
+            if ((int)threadIdx.x < nc) st->c2[threadIdx.x] = (double)(sc[threadIdx.x] + (corr ? c2 : A(0)));
             if (threadIdx.x == 0) {
-                st->wnorm2 = w1;
+                st->wnorm2 = (double)w1;
                 st->second = 1;
                 // alpha_j = v_j . A v_j = c_j + beta_j (v_j . v_{j-1}), with
                 // w = A v_j - beta_j v_{j-1}; the SpMV does not reduce it in
                 // these modes.
                 if (st->mode == MODE_NORMAL)
-                    st->alpha[j] = sc[j] + (j > 0 ? st->beta[j] * gm[j * NCMAX + (j - 1)] : 0.0);
+                    st->alpha[j] = (double)(sc[j] + (j > 0 ? (A)st->beta[j] * (A)gm[j * NCMAX + (j - 1)] : A(0)));
             }
         } else if (!upd_dot_active(st)) {  // one pass: the store kernel uses c
             for (int k = threadIdx.x; k < nc; k += OBLOCK) st->c2[k] = st->c[k];
@@ -314,19 +326,19 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
 
 // Partial update u = sum_k V[rows, k] coef[k] over this lane's columns,
 // completed over the CS lanes of the row group.
-template <int P, int NC>
-__device__ __forceinline__ void split_update(const typename Ch<P>::T (&ch)[Split<P, NC>::NCL], const double* coef,
-                                             int cs, int lo, int nc, double (&u)[Ch<P>::R]) {
+template <int P, int NC, class A>
+__device__ __forceinline__ void split_update(const typename Ch<P>::T (&ch)[Split<P, NC>::NCL], const A* coef,
+                                             int cs, int lo, int nc, A (&u)[Ch<P>::R]) {
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL;
 #pragma unroll
-    for (int rr = 0; rr < R; ++rr) u[rr] = 0.0;
+    for (int rr = 0; rr < R; ++rr) u[rr] = A(0);
 #pragma unroll
     for (int kk = 0; kk < NCL; ++kk) {
         const int k = cs * NCL + kk;
         if (k >= lo && k < nc) {
-            double v[R];
+            A v[R];
             unpack(ch[kk], v);
-            const double cf = coef[k];
+            const A cf = coef[k];
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) u[rr] += v[rr] * cf;
         }
@@ -338,16 +350,16 @@ __device__ __forceinline__ void split_update(const typename Ch<P>::T (&ch)[Split
 }
 
 // w' = w - V c (stored in the working precision), then c2 = V^T w' and ||w'||^2.
-template <int P, int NC>
+template <int P, int NC, class A>
 __global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                         typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                         double* part, double* part2) {
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
-    __shared__ double coef[NC];
-    __shared__ double red[OWAVES][NC];
-    __shared__ double shd[OWAVES];
-    __shared__ double sred[OBLOCK];
+    __shared__ A coef[NC];
+    __shared__ A red[OWAVES][NC];
+    __shared__ A shd[OWAVES];
+    __shared__ A sred[OBLOCK];
     __shared__ int s_last;
     const int j = st->j;
     if (st->status != 0 || j >= st->m || !upd_dot_active(st)) return;
@@ -356,19 +368,19 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typena
         if (blockIdx.x == 0 && threadIdx.x == 0) st->status = -1;
         return;
     }
-    for (int k = threadIdx.x; k < NC; k += OBLOCK) coef[k] = k < nc ? st->c[k] * st->scale[k] : 0.0;
+    for (int k = threadIdx.x; k < NC; k += OBLOCK) coef[k] = k < nc ? (A)st->c[k] * (A)st->scale[k] : A(0);
     __syncthreads();
     const int ln = threadIdx.x & 63, cs = ln % CS;
     constexpr int64_t RBW = (int64_t)GPW * R;
     const int64_t lane_row = (int64_t)(ln / CS) * R;
     const int64_t wave0 = (int64_t)blockIdx.x * OWAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double acc[NCL];
+    A acc[NCL];
 #pragma unroll
-    for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
-    double nrm = 0.0;
+    for (int kk = 0; kk < NCL; ++kk) acc[kk] = A(0);
+    A nrm = A(0);
     for (int64_t base = wave0 * RBW; base < ld; base += (int64_t)gridDim.x * OWAVES * RBW) {
         const int64_t r0 = base + lane_row;
-        double x[R];
+        A x[R];
         w_load(w + r0, x);
         CT ch[NCL];
 #pragma unroll
@@ -376,7 +388,7 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typena
             const int k = cs * NCL + kk;
             if (k < nc) ch[kk] = *(const CT*)(Vb + (int64_t)k * ld + r0);
         }
-        double u[R];
+        A u[R];
         split_update<P, NC>(ch, coef, cs, 0, nc, u);
 #pragma unroll
         for (int kk = 0; kk < NCL; ++kk) opaque(ch[kk]);
@@ -390,9 +402,9 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typena
         for (int kk = 0; kk < NCL; ++kk) {
             const int k = cs * NCL + kk;
             if (k < nc) {
-                double v[R];
+                A v[R];
                 unpack(ch[kk], v);
-                double s = 0.0;
+                A s = A(0);
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) s += v[rr] * x[rr];
                 acc[kk] += s;
@@ -401,18 +413,18 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typena
     }
     publish_split<NC, CS, NCL>(acc, nc, part, red);
     nrm = block_sum(nrm, shd, OWAVES);
-    if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
+    if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], (double)nrm);
     if (last_block(&st->ticket[TK_UPD], gridDim.x, &s_last)) {
-        const double wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c2, sred, shd);
+        const A wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c2, sred, shd);
         if (threadIdx.x == 0) {
-            st->wnorm2 = wn;
+            st->wnorm2 = (double)wn;
             int second = 1;
             if (st->reorth == 3 && st->mode != MODE_RESTART) {
                 // Selective: skip the second update when its correction is
                 // below the rounding of the stored vector.
-                double c2n = 0.0;
-                for (int k = 0; k < nc; ++k) c2n += st->c2[k] * st->c2[k];
-                second = c2n > st->u_s * st->u_s * wn;
+                A c2n = A(0);
+                for (int k = 0; k < nc; ++k) c2n += (A)st->c2[k] * (A)st->c2[k];
+                second = c2n > (A)(st->u_s * st->u_s) * wn;
             }
             st->second = second;
         }
@@ -425,17 +437,18 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typena
 // the working vector, starts a restart).  In the
 // two-pass modes the same pass takes the dots of the stored column with the
 // basis: the new row and column of the Gram matrix.
-template <int P, int NC, bool GRAM>
+template <int P, int NC, bool GRAM, class A>
 __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename Tr<P>::V* __restrict__ Vb,
                                                           const typename Tr<P>::W* __restrict__ w, int64_t ld,
                                                           double* part, double* part2, double* gm) {
     using CT = typename Ch<P>::T;
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
-    __shared__ double coef[NC];
-    __shared__ double red[OWAVES][NC];
+    __shared__ A coef[NC];
+    __shared__ A red[OWAVES][NC];
     __shared__ double gcol[NC];
+    __shared__ A sha[OWAVES];
     __shared__ double shd[OWAVES];
-    __shared__ double sred[OBLOCK];
+    __shared__ A sred[OBLOCK];
     __shared__ int s_last, s_accept;
     const int j = st->j;
     if (st->status != 0 || j >= st->m) return;
@@ -450,20 +463,20 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
     constexpr bool gram = GRAM;
     const int lo = (!GRAM && st->reorth == 0 && st->mode != MODE_RESTART) ? j : 0;
     for (int k = threadIdx.x; k < NC; k += OBLOCK)
-        coef[k] = (second && k >= lo && k < nc) ? st->c2[k] * st->scale[k] : 0.0;
+        coef[k] = (second && k >= lo && k < nc) ? (A)st->c2[k] * (A)st->scale[k] : A(0);
     __syncthreads();
     const int ln = threadIdx.x & 63, cs = ln % CS;
     constexpr int64_t RBW = (int64_t)GPW * R;
     const int64_t lane_row = (int64_t)(ln / CS) * R;
     const int64_t wave0 = (int64_t)blockIdx.x * OWAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     auto* out = Vb + (int64_t)(j + 1) * ld;
-    double nrm = 0.0;
-    double acc[NCL];
+    A nrm = A(0);
+    A acc[NCL];
 #pragma unroll
-    for (int kk = 0; kk < NCL; ++kk) acc[kk] = 0.0;
+    for (int kk = 0; kk < NCL; ++kk) acc[kk] = A(0);
     for (int64_t base = wave0 * RBW; base < ld; base += (int64_t)gridDim.x * OWAVES * RBW) {
         const int64_t r0 = base + lane_row;
-        double x[R];
+        A x[R];
         w_load(w + r0, x);
         if (second) {
             CT ch[NCL];
@@ -472,7 +485,7 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
                 const int k = cs * NCL + kk;
                 if (k >= lo && k < nc) ch[kk] = *(const CT*)(Vb + (int64_t)k * ld + r0);
             }
-            double u[R];
+            A u[R];
             split_update<P, NC>(ch, coef, cs, lo, nc, u);
 #pragma unroll
             for (int kk = 0; kk < NCL; ++kk) opaque(ch[kk]);
@@ -484,9 +497,9 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
                 for (int kk = 0; kk < NCL; ++kk) {
                     const int k = cs * NCL + kk;
                     if (k < nc) {
-                        double v[R];
+                        A v[R];
                         unpack(ch[kk], v);
-                        double s = 0.0;
+                        A s = A(0);
 #pragma unroll
                         for (int rr = 0; rr < R; ++rr) s += v[rr] * x[rr];
                         acc[kk] += s;
@@ -500,13 +513,13 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
             for (int rr = 0; rr < R; ++rr) nrm += x[rr] * x[rr];
     }
     if (gram) publish_split<NC, CS, NCL>(acc, nc, part, red);
-    nrm = block_sum(nrm, shd, OWAVES);
-    if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], nrm);
+    nrm = block_sum(nrm, sha, OWAVES);
+    if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], (double)nrm);
     if (last_block(&st->ticket[TK_STORE], gridDim.x, &s_last)) {
-        const double tot = gram ? reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, gcol, sred, shd)
-                                : ordered_sum_dev(part2, gridDim.x, shd);
+        const A tot = gram ? reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, gcol, sred, sha)
+                           : (A)ordered_sum_dev(part2, gridDim.x, shd);
         if (threadIdx.x == 0) {
-            const double b = sqrt(tot);
+            const A b = sqrt(tot);
             int accept = 0;
             if (!isfinite(b)) {
                 st->status = -7;               // LZ_ERR_NONFINITE
@@ -522,8 +535,8 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
                     st->restarts += 1;
                     st->beta[j + 1] = 0.0;
                 } else {
-                    st->beta[j + 1] = b;
-                    st->scale[j + 1] = b > 0.0 ? 1.0 / b : 0.0;
+                    st->beta[j + 1] = (double)b;
+                    st->scale[j + 1] = b > A(0) ? (double)(A(1) / b) : 0.0;
                     st->j = j + 1;
                     accept = 1;
                 }
@@ -532,7 +545,7 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
                     st->status = -8;           // LZ_ERR_BREAKDOWN
                     st->j = st->m;
                 } else {
-                    st->scale[j + 1] = 1.0 / b;
+                    st->scale[j + 1] = (double)(A(1) / b);
                     st->beta[j + 1] = 0.0;
                     st->mode = MODE_NORMAL;
                     st->j = j + 1;
@@ -545,13 +558,13 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
         if (gram && s_accept) {
             // Gram entries of the unit stored vectors: column j+1 against 0..j
             // (gcol already carries scale_k) and its own squared norm.
-            const double sn = st->scale[j + 1];
+            const A sn = (A)st->scale[j + 1];
             for (int k = threadIdx.x; k < nc; k += OBLOCK) {
-                const double g = gcol[k] * sn;
+                const double g = (double)((A)gcol[k] * sn);
                 gm[k * NCMAX + (j + 1)] = g;
                 gm[(j + 1) * NCMAX + k] = g;
             }
-            if (threadIdx.x == 0) gm[(j + 1) * NCMAX + (j + 1)] = tot * sn * sn;
+            if (threadIdx.x == 0) gm[(j + 1) * NCMAX + (j + 1)] = (double)(tot * sn * sn);
         }
     }
 }
@@ -559,9 +572,9 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
 // ---------------------------------------------------------------- launchers
 static inline int nc_bucket(int ncols) { return ((ncols + 7) / 8) * 8; }
 
-template <int P>
-static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int ncols, int reorth, hipStream_t s,
-                              hipEvent_t* ev) {
+template <int P, class A>
+static hipError_t iteration_pa(const Plan& p, const Bufs& b, const Csr& a, int ncols, int reorth, hipStream_t s,
+                               hipEvent_t* ev) {
     using VT = typename Tr<P>::V;
     using WT = typename Tr<P>::W;
     VT* V = (VT*)b.V;
@@ -572,16 +585,16 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
     const int nb = nc_bucket(ncols);
 #define LZ_ORTH_CASE(NCV)                                                                                  \
     case NCV:                                                                                              \
-        hipLaunchKernelGGL((k_orth_dot<P, NCV>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w, p.ld,      \
+        hipLaunchKernelGGL((k_orth_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w, p.ld,      \
                            b.part, b.part2, b.gm);                                                         \
         if (reorth < 2)                                                                                    \
-            hipLaunchKernelGGL((k_orth_upd_dot<P, NCV>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w,    \
+            hipLaunchKernelGGL((k_orth_upd_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w,    \
                                p.ld, b.part, b.part2);                                                     \
         if (reorth >= 2)                                                                                   \
-            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, true>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, \
+            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, true, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, \
                                w, p.ld, b.part, b.part2, b.gm);                                            \
         else                                                                                               \
-            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, false>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st,  \
+            hipLaunchKernelGGL((k_orth_upd_store<P, NCV, false, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st,  \
                                V, w, p.ld, b.part, b.part2, b.gm);                                         \
         break;
     switch (nb) {
@@ -603,9 +616,11 @@ static hipError_t iteration_p(const Plan& p, const Bufs& b, const Csr& a, int nc
 hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols, int reorth, hipStream_t s,
                             hipEvent_t* ev) {
     switch (p.prec) {
-        case 0: return iteration_p<0>(p, b, a, ncols, reorth, s, ev);
-        case 1: return iteration_p<1>(p, b, a, ncols, reorth, s, ev);
-        case 2: return iteration_p<2>(p, b, a, ncols, reorth, s, ev);
+        case 0: return iteration_pa<0, double>(p, b, a, ncols, reorth, s, ev);
+        case 1:
+            return p.fff ? iteration_pa<1, float>(p, b, a, ncols, reorth, s, ev)
+                         : iteration_pa<1, double>(p, b, a, ncols, reorth, s, ev);
+        case 2: return iteration_pa<2, double>(p, b, a, ncols, reorth, s, ev);
     }
     return hipErrorInvalidValue;
 }

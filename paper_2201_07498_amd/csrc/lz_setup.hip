@@ -29,7 +29,8 @@ constexpr double REORDER_SKEW = 32.0;
 constexpr int CHR = 4096;          // rows per counting-sort chunk (one workgroup)
 constexpr int NKEY = 64;           // degree classes
 
-__global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double u_s, double u_w, uint64_t seed) {
+__global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double u_s, double u_w, uint64_t seed,
+                        int arith) {
     uint64_t* p = reinterpret_cast<uint64_t*>(st);
     const size_t words = sizeof(State) / 8;
     for (size_t i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0ull;
@@ -42,6 +43,7 @@ __global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double
         st->u_s = u_s;
         st->u_w = u_w;
         st->seed = seed;
+        st->arith = arith;
     }
 }
 
@@ -357,7 +359,7 @@ bool host_relabel_decision(const int64_t* rp, int64_t n, int64_t nnz, int reorde
 hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t seed, int reorth, int reorder,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, b.st, p.m, p.K, reorth, reorder, unit_roundoff(p.prec),
-                       work_roundoff(p.prec), seed);
+                       work_roundoff(p.prec), seed, p.fff);
     const int64_t n = a.n, nnz = a.nnz;
     const int g = (int)std::min<int64_t>((n + BLOCK - 1) / BLOCK, 8192);
     const int gv = (int)std::min<int64_t>((std::max(n, nnz) + BLOCK - 1) / BLOCK, 1024);

@@ -21,7 +21,12 @@ namespace lz {
 constexpr int XW = 16;                 // wavefronts per workgroup of the cached variant
 constexpr int XC_BYTES = 64 * 1024;
 
-template <int P, int NW, bool XCACHE>
+// Arithmetic of the epilogue (scale, beta term, alpha partials): double, or
+// float in the all-FP32 mode.
+template <bool F> struct Epi { using T = double; };
+template <> struct Epi<true> { using T = float; };
+
+template <int P, int NW, bool XCACHE, bool F = false>
 __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                        typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
                                                        int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
@@ -29,8 +34,9 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
+    using E = typename Epi<F>::T;
     constexpr int H = XCACHE ? XC_BYTES / (int)sizeof(VT) : 1;
-    __shared__ double shd[NW];
+    __shared__ E shd[NW];
     __shared__ int s_last;
     __shared__ VT xs[H];
     if (st->status != 0) return;
@@ -50,23 +56,23 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
     const VT* val = (const VT*)st->cval;
     const VT* x = Vb + (int64_t)j * ld;
     const VT* xp = j > 0 ? Vb + (int64_t)(j - 1) * ld : nullptr;
-    const double sj = st->scale[j];
-    const double bsc = j > 0 ? st->beta[j] * st->scale[j - 1] : 0.0;
-    double apart = 0.0;
+    const E sj = (E)st->scale[j];
+    const E bsc = j > 0 ? (E)st->beta[j] * (E)st->scale[j - 1] : E(0);
+    E apart = E(0);
     // alpha = sum_r (sj x_r)(sj acc_r) is linear in every row sum, so a split
     // row adds one term per piece and the w update waits for the whole sum.
     // In the two-pass modes alpha comes from the first Gram-Schmidt pass
     // (alpha_j = c_j + beta_j v_j . v_{j-1}); only the other modes reduce it here.
     const bool need_alpha = st->reorth < 2;
     auto row = [&](int64_t r, double acc) {
-        const double y = sj * acc;
-        if (need_alpha) apart += sj * to_d(x[r]) * y;
-        w[r] = (WT)(y - (xp ? bsc * to_d(xp[r]) : 0.0));
+        const E y = sj * (E)acc;
+        if (need_alpha) apart += sj * (E)to_d(x[r]) * y;
+        w[r] = (WT)(y - (xp ? bsc * (E)to_d(xp[r]) : E(0)));
     };
     auto piece = [&](int64_t r, double acc) {
-        if (need_alpha) apart += sj * to_d(x[r]) * (sj * acc);
+        if (need_alpha) apart += sj * (E)to_d(x[r]) * (sj * (E)acc);
     };
-    auto fin = [&](int64_t r, double acc) { w[r] = (WT)(sj * acc - (xp ? bsc * to_d(xp[r]) : 0.0)); };
+    auto fin = [&](int64_t r, double acc) { w[r] = (WT)(sj * (E)acc - (xp ? bsc * (E)to_d(xp[r]) : E(0))); };
     int hn = 0;
     if constexpr (XCACHE) {
         hn = (int)min<int64_t>(H, n);
@@ -76,9 +82,10 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
     spmv_tiles<VT, AT, NW, XCACHE>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, row, piece, fin);
     if (!need_alpha) return;
     apart = block_sum(apart, shd, NW);
-    if (threadIdx.x == 0) st_dev(&part[blockIdx.x], apart);
+    if (threadIdx.x == 0) st_dev(&part[blockIdx.x], (double)apart);
+    __shared__ double shs[NW];
     if (last_block(&st->ticket[TK_SPMV], gridDim.x, &s_last)) {
-        const double alpha = ordered_sum_dev(part, gridDim.x, shd);
+        const double alpha = (double)(E)ordered_sum_dev(part, gridDim.x, shs);
         if (threadIdx.x == 0) {
             st->alpha[j] = alpha;
             if (st->reorth == 0) {          // three-term recurrence only
@@ -108,7 +115,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
 }
 
 // ---------------------------------------------------------------- launchers
-template <int P>
+template <int P, bool F = false>
 static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
     using VT = typename Tr<P>::V;
     using WT = typename Tr<P>::W;
@@ -116,13 +123,14 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
         hipLaunchKernelGGL((k_spmv_step<P, WAVES, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V,
                            (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
     } else if (!p.xcache) {
-        hipLaunchKernelGGL((k_spmv_step<P, WAVES, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V,
-                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+        hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st,
+                           (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
+                           b.part2);
     } else {
         // One workgroup of XW wavefronts per CU (its LDS holds the x head).
         const int64_t g = std::min<int64_t>(256, (p.n_tiles + XW - 1) / XW);
         const int gx = (int)((g + 7) / 8 * 8);
-        hipLaunchKernelGGL((k_spmv_step<P, XW, true>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
+        hipLaunchKernelGGL((k_spmv_step<P, XW, true, F>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
                            (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
     }
 }
@@ -130,7 +138,12 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
 void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
     switch (p.prec) {
         case 0: spmv_step_p<0>(p, b, a, s); break;
-        case 1: spmv_step_p<1>(p, b, a, s); break;
+        case 1:
+            if (p.fff)
+                spmv_step_p<1, true>(p, b, a, s);
+            else
+                spmv_step_p<1>(p, b, a, s);
+            break;
         default: spmv_step_p<2>(p, b, a, s); break;
     }
 }

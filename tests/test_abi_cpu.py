@@ -40,9 +40,13 @@ def test_status_strings_and_defaults():
     L.lz_options_init(ctypes.byref(opt))
     assert opt.reorth == 2 and opt.report == 1 and opt.seed == 0 and not opt.workspace
     assert opt.reorder == lz.REORDER["auto"]
+    assert opt.arith == lz.ARITH["mixed"]
 
 
-@pytest.mark.parametrize("field,value", [("reorder", 3), ("reorder", -1), ("reorth", 4)])
+# The solve below is FP64, so the all-FP32 arithmetic (FP32 storage only) is
+# rejected as well as out-of-range values.
+@pytest.mark.parametrize("field,value", [("reorder", 3), ("reorder", -1), ("reorth", 4), ("arith", 2),
+                                         ("arith", -1), ("arith", 1)])
 def test_invalid_options_rejected_without_gpu(field, value):
     L = lz.lib()
     d = ctypes.c_void_p(16)
