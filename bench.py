@@ -321,6 +321,49 @@ def study_reorth(args, W, lz, torch, device_csr, eig_rel_err):
     print(json.dumps({"study": "reorth", "workload": args.workload, "n": n, "nnz": nnz, "rows": rows}), flush=True)
 
 
+def study_precision(args, lz, torch, device_csr, eig_rel_err):
+    """Sec. IV-D precision trade-off: per matrix, solve time and error of the
+    all-double (DDD), FP32-storage/FP64-arithmetic (FDF) and all-FP32 (FFF)
+    configurations.  Errors are against the FP64 oracle: Ritz values, basis
+    orthogonality, and the residual ||A y - theta y|| of the leading pair
+    (the pair every configuration converges)."""
+    import oracle
+    import synth
+    mats = [("er n=1e4", lambda: synth.er(10000, 9.0, seed=0)),
+            ("er n=1e5", lambda: synth.er(100000, 9.0, seed=1)),
+            ("rmat 14", lambda: synth.rmat(14, 8, seed=2)),
+            ("rmat 16", lambda: synth.rmat(16, 8, seed=3)),
+            ("rmat 18", lambda: synth.rmat(18, 8, seed=4))]
+    K, m = 8, 24
+    rows = []
+    for name, gen in mats:
+        rp, col, val = gen()
+        val = synth.round_values(val, "fp32")          # every configuration sees one matrix
+        n, nnz = rp.size - 1, int(rp[-1])
+        ref = oracle.topk(rp, col, val, K, m, seed=0)
+        for label, mode in (("DDD", "fp64"), ("FDF", "fp32"), ("FFF", "fp32-fff")):
+            prec, arith = mode_of(mode)
+            dcsr = device_csr(rp, col, val, prec, torch.device("cuda:0"))
+            lz.topk(*dcsr, K, m, prec, seed=0, arith=arith)
+            torch.cuda.synchronize()
+            reps = max(1, min(args.steps, 10))
+            t = time.perf_counter()
+            for _ in range(reps):
+                vals, _, rep = lz.topk(*dcsr, K, m, prec, seed=0, arith=arith)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / reps
+            row = {"matrix": name, "n": n, "nnz": nnz, "config": label, "ms_per_solve": dt * 1e3,
+                   "eig_rel_err": eig_rel_err(vals.cpu().numpy(), ref["vals"]),
+                   "ortho_loss": rep["ortho_loss"], "ritz_ortho_loss": rep["ritz_ortho_loss"],
+                   "lead_abs_resid": float(rep["abs_resid"][0]), "oracle_lead_abs_resid": float(ref["abs_resid"][0])}
+            rows.append(row)
+            print(f"[study] {name:9s} {label}: {dt * 1e3:7.3f} ms  eig err {row['eig_rel_err']:.2e}  ortho "
+                  f"{row['ortho_loss']:.1e}  lead resid {row['lead_abs_resid']:.2e} (oracle "
+                  f"{row['oracle_lead_abs_resid']:.2e})", file=sys.stderr, flush=True)
+            del dcsr
+    print(json.dumps({"study": "precision", "K": K, "m": m, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,9 +381,11 @@ def main():
                     help="first run a plain copy kernel (1 GiB read + 1 GiB written, three launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic of the other kernels")
     ap.add_argument("--precisions", default=None, help="comma list overriding the workload's precisions")
-    ap.add_argument("--study", default=None, choices=["reorth"],
+    ap.add_argument("--study", default=None, choices=["reorth", "precision"],
                     help="reorth: accuracy and time of the reorthogonalisation modes (none/once/twice/"
-                         "selective) for K in {8, 16, 32}, m = 3K, on the workload; prints one JSON line")
+                         "selective) for K in {8, 16, 32}, m = 3K, on the workload; precision: all-double, "
+                         "FP32 storage and all-FP32 arithmetic on seeded ER and R-MAT matrices against the "
+                         "oracle; each prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -373,6 +418,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.study == "reorth":
         return study_reorth(args, W, lz, torch, device_csr, eig_rel_err)
+    if args.study == "precision":
+        return study_precision(args, lz, torch, device_csr, eig_rel_err)
     ws_bytes = max(lz.workspace_size(n, nnz, K, m, mode_of(p)[0]) for p in W["precisions"])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 

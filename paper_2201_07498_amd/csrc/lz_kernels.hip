@@ -236,6 +236,7 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
     constexpr int R = Ch<P>::R, CS = Split<P, NC>::CS, NCL = Split<P, NC>::NCL, GPW = 64 / CS;
     __shared__ A red[OWAVES][NC];
     __shared__ A sc[NC];
+    __shared__ A sg[NC][NC + 1];
     __shared__ A shd[OWAVES];
     __shared__ A sred[OBLOCK];
     __shared__ int s_last;
@@ -284,8 +285,22 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
     nrm = block_sum(nrm, shd, OWAVES);
     if (threadIdx.x == 0) st_dev(&part2[blockIdx.x], (double)nrm);
     if (last_block(&st->ticket[TK_DOT], gridDim.x, &s_last)) {
+        // The Gram rows the correction needs are loaded in the same round of
+        // requests as the partials (nc^2 <= 4 * OBLOCK entries).
+        const bool gram = gram_mode(st);
+        A gv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = threadIdx.x + q * OBLOCK;
+            gv[q] = (gram && idx < nc * nc) ? (A)gm[(idx / nc) * NCMAX + idx % nc] : A(0);
+        }
         const A wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c, sred, shd);
-        if (gram_mode(st)) {
+        if (gram) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = threadIdx.x + q * OBLOCK;
+                if (idx < nc * nc) sg[idx / nc][idx % nc] = gv[q];
+            }
             // Second coefficients of classical Gram-Schmidt without a second
             // pass: V^T (w - V c) = c - G c, G the Gram matrix of the unit
             // stored basis.  The update then subtracts V (c + c2) at once, in
@@ -295,21 +310,25 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
             A c2 = A(0);
             if ((int)threadIdx.x < nc) {
                 A gc = A(0);
-                for (int l = 0; l < nc; ++l) gc += (A)gm[threadIdx.x * NCMAX + l] * sc[l];
+                for (int l = 0; l < nc; ++l) gc += sg[threadIdx.x][l] * sc[l];
                 c2 = sc[threadIdx.x] - gc;
             }
             // Selective: skip the correction when it is below the rounding of
             // the stored vector, ||c2|| <= u_s ||w - V c||, with
-            // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c).
-            A sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : A(0),
-                        (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : A(0),
-                        (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : A(0)};
-            for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
-            const A w1 = fmax(A(0), wn - A(2) * sel[1] + sel[2]);
-            const bool corr = st->reorth == 2 || st->mode == MODE_RESTART || sel[0] > (A)(st->u_s * st->u_s) * w1;
+            // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c).  The two-pass mode
+            // and restart vectors always apply it.
+            bool corr = true;
+            if (st->reorth == 3 && st->mode != MODE_RESTART) {
+                A sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : A(0),
+                            (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : A(0),
+                            (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : A(0)};
+                for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
+                const A w1 = fmax(A(0), wn - A(2) * sel[1] + sel[2]);
+                corr = sel[0] > (A)(st->u_s * st->u_s) * w1;
+                if (threadIdx.x == 0) st->wnorm2 = (double)w1;
+            }
             if ((int)threadIdx.x < nc) st->c2[threadIdx.x] = (double)(sc[threadIdx.x] + (corr ? c2 : A(0)));
             if (threadIdx.x == 0) {
-                st->wnorm2 = (double)w1;
                 st->second = 1;
                 // alpha_j = v_j . A v_j = c_j + beta_j (v_j . v_{j-1}), with
                 // w = A v_j - beta_j v_{j-1}; the SpMV does not reduce it in
@@ -450,6 +469,13 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
     __shared__ double shd[OWAVES];
     __shared__ A sred[OBLOCK];
     __shared__ int s_last, s_accept;
+    // The coefficients do not depend on the step index: their loads go out
+    // with it.
+    double c2k = 0.0, sk = 0.0;
+    if ((int)threadIdx.x < NC) {
+        c2k = st->c2[threadIdx.x];
+        sk = st->scale[threadIdx.x];
+    }
     const int j = st->j;
     if (st->status != 0 || j >= st->m) return;
     const int nc = j + 1;
@@ -462,8 +488,10 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_store(State* st, typename T
     const bool second = GRAM || st->second != 0;
     constexpr bool gram = GRAM;
     const int lo = (!GRAM && st->reorth == 0 && st->mode != MODE_RESTART) ? j : 0;
-    for (int k = threadIdx.x; k < NC; k += OBLOCK)
-        coef[k] = (second && k >= lo && k < nc) ? (A)st->c2[k] * (A)st->scale[k] : A(0);
+    if ((int)threadIdx.x < NC) {
+        const int k = threadIdx.x;
+        coef[k] = (second && k >= lo && k < nc) ? (A)c2k * (A)sk : A(0);
+    }
     __syncthreads();
     const int ln = threadIdx.x & 63, cs = ln % CS;
     constexpr int64_t RBW = (int64_t)GPW * R;
