@@ -21,9 +21,11 @@
 // piece to arrive adds all of them in tile order, so the row sum does not
 // depend on which wavefront finishes last.
 //
-// The epilogue is three callbacks, all called by one lane with a value that
-// is final for that lane:
-//   row(r, s)    owned row r with its whole sum s;
+// The epilogue is four callbacks, all called by one lane:
+//   pre(r)       a value the row epilogue needs (e.g. an entry of another
+//                vector), loaded for the first 64 owned rows together with
+//                the tile's entries;
+//   row(r, s, p) owned row r with its whole sum s and p = pre(r);
 //   piece(r, s)  one piece of a split row (for sums that are linear in the
 //                row sum, such as alpha);
 //   fin(r, s)    a split row's whole sum, from the finalising wavefront.
@@ -123,12 +125,16 @@ __device__ __forceinline__ double split_total(const double* head, const double* 
 
 // NW wavefronts per workgroup.  With CACHED, xs holds x[0..hn) in LDS and
 // gathers of those entries read it instead of global memory.
-template <class VT, class AT, int NW, bool CACHED, class Row, class Piece, class Fin>
+// The row bounds of the first 64 owned rows, pre() of those rows and the
+// start of the row continuing past the tile are loaded with the tile's
+// entries, so a tile waits for two rounds of requests (entries, then
+// gathers) before its sums are written.
+template <class VT, class AT, int NW, bool CACHED, class Pre, class Row, class Piece, class Fin>
 __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const VT* __restrict__ x, const VT* xs,
                                            int hn, int64_t n, int64_t nnz, int64_t n_tiles,
                                            const int32_t* __restrict__ ob, uint32_t* tk, double* head, double* tail,
-                                           Row&& row, Piece&& piece, Fin&& fin) {
+                                           Pre&& pre, Row&& row, Piece&& piece, Fin&& fin) {
     __shared__ AT prod[NW][TILE];
     const int lane = threadIdx.x & 63;
     AT* pw = prod[threadIdx.x >> 6];
@@ -149,6 +155,17 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
             n_lo = ob[tn];
             n_hi = ob[tn + 1];
         }
+        // Bounds and epilogue operands of the first 64 owned rows, and the
+        // start of the continuing row.
+        const int64_t r_first = r_lo + lane;
+        int64_t rb0 = 0, re0 = 0;
+        double pv0 = 0.0;
+        if (r_first < r_hi) {
+            rb0 = rp[r_first];
+            re0 = rp[r_first + 1];
+            pv0 = pre(r_first);
+        }
+        const int64_t rb_hi = r_hi < n ? rp[r_hi] : 0;
         // Entries of the tile, then the gathers of x.  Lanes past the end
         // re-read the tile's last entry (same cache line), so every load is
         // unconditional; their products land beyond cnt and are never read.
@@ -173,15 +190,18 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
         }
         wave_sync();
         // Owned rows, 64 at a time.
-        const bool split_head = r_lo < r_hi && rp[r_lo] < t0;
+        const bool split_head = r_lo < r_hi && __shfl(rb0, 0, 64) < t0;
         double head_s = 0.0;
         for (int64_t base = r_lo; base < r_hi; base += 64) {
             const int64_t r = base + lane;
             const bool valid = r < r_hi;
+            const bool first = base == r_lo;
             int b = 0, e = 0;
+            double pv = 0.0;
             if (valid) {
-                b = (int)(max(rp[r], t0) - t0);
-                e = (int)(rp[r + 1] - t0);
+                b = (int)(max(first ? rb0 : rp[r], t0) - t0);
+                e = (int)((first ? re0 : rp[r + 1]) - t0);
+                pv = first ? pv0 : pre(r);
             }
             const bool islong = valid && e - b > LONGR;
             AT s = (valid && !islong) ? lds_sum(pw, b, e) : AT(0);
@@ -197,7 +217,7 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
                     head_s = (double)s;
                     piece(r, head_s);
                 } else {
-                    row(r, (double)s);
+                    row(r, (double)s, pv);
                 }
             }
         }
@@ -212,7 +232,7 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
         }
         // Tail piece of the row that continues past this tile.
         if (r_hi < n) {
-            const int64_t rb = rp[r_hi];
+            const int64_t rb = rb_hi;
             if (rb < t0 + cnt) {
                 const AT ss = lds_wave_sum(pw, (int)(max(rb, t0) - t0), cnt, lane);
                 if (lane == 0) {

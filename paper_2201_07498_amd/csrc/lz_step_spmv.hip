@@ -64,10 +64,11 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
     // In the two-pass modes alpha comes from the first Gram-Schmidt pass
     // (alpha_j = c_j + beta_j v_j . v_{j-1}); only the other modes reduce it here.
     const bool need_alpha = st->reorth < 2;
-    auto row = [&](int64_t r, double acc) {
+    auto pre = [&](int64_t r) { return xp ? to_d(xp[r]) : 0.0; };
+    auto row = [&](int64_t r, double acc, double xpr) {
         const E y = sj * (E)acc;
         if (need_alpha) apart += sj * (E)to_d(x[r]) * y;
-        w[r] = (WT)(y - (xp ? bsc * (E)to_d(xp[r]) : E(0)));
+        w[r] = (WT)(y - bsc * (E)xpr);
     };
     auto piece = [&](int64_t r, double acc) {
         if (need_alpha) apart += sj * (E)to_d(x[r]) * (sj * (E)acc);
@@ -79,7 +80,8 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
         for (int i = threadIdx.x; i < hn; i += NW * 64) xs[i] = x[i];
         __syncthreads();
     }
-    spmv_tiles<VT, AT, NW, XCACHE>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, row, piece, fin);
+    spmv_tiles<VT, AT, NW, XCACHE>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, pre, row, piece,
+                                   fin);
     if (!need_alpha) return;
     apart = block_sum(apart, shd, NW);
     if (threadIdx.x == 0) st_dev(&part[blockIdx.x], (double)apart);
@@ -110,8 +112,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
     using WT = typename Tr<P>::W;
     if (st->status != 0) return;
     spmv_tiles<VT, AT, WAVES, false>(
-        rp, col, val, x, nullptr, 0, n, nnz, n_tiles, ob, tk, head, tail, [&](int64_t r, double acc) { y[r] = (WT)acc; },
-        [&](int64_t, double) {}, [&](int64_t r, double acc) { y[r] = (WT)acc; });
+        rp, col, val, x, nullptr, 0, n, nnz, n_tiles, ob, tk, head, tail, [](int64_t) { return 0.0; },
+        [&](int64_t r, double acc, double) { y[r] = (WT)acc; }, [&](int64_t, double) {},
+        [&](int64_t r, double acc) { y[r] = (WT)acc; });
 }
 
 // ---------------------------------------------------------------- launchers
