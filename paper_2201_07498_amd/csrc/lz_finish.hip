@@ -377,17 +377,22 @@ __device__ __forceinline__ double group_sum(double v, int KB2) {
     return v;
 }
 
+// The matrix arrays come in as kernel arguments (the caller's CSR and the
+// relabelled copy), so their loads are global loads, as in the step SpMV.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restrict__ Y, double* __restrict__ Z,
                                                 int64_t n, int64_t nnz, int64_t n_tiles, const int32_t* __restrict__ ob,
-                                                uint32_t* tk, double* head, double* tail, int KB2) {
+                                                uint32_t* tk, double* head, double* tail, int KB2,
+                                                const int64_t* rp_a, const int32_t* col_a, const void* val_a,
+                                                const int64_t* rp_b, const int32_t* col_b, const void* val_b) {
     using VT = typename Tr<P>::V;
     __shared__ int scol_all[WAVES][TILE];
     __shared__ VT sval_all[WAVES][TILE];
     if (st->status != 0) return;
-    const int64_t* rp = st->crp;
-    const int32_t* col = st->ccol;
-    const VT* val = (const VT*)st->cval;
+    const bool rl = st->reordered != 0;
+    const int64_t* rp = rl ? rp_b : rp_a;
+    const int32_t* col = rl ? col_b : col_a;
+    const VT* val = (const VT*)(rl ? val_b : val_a);
     const int K = st->K;
     const int lane = threadIdx.x & 63;
     const int G = 64 / KB2, g = lane / KB2, k = lane % KB2;
@@ -726,7 +731,7 @@ static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* o
     hipLaunchKernelGGL(k_colstats, dim3(gc), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, b.part);
     if (report)
         hipLaunchKernelGGL((k_spmm<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, b.Y, b.Z, p.n, p.nnz, p.n_tiles,
-                           b.ob, b.tk, b.head, b.tail, kb2);
+                           b.ob, b.tk, b.head, b.tail, kb2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
     const int go = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (p.n + 63) / 64));
     hipLaunchKernelGGL(k_out, dim3(go), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, out_vecs);
     if (!report) return hipGetLastError();

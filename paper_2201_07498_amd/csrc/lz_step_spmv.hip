@@ -26,11 +26,18 @@ constexpr int XC_BYTES = 64 * 1024;
 template <bool F> struct Epi { using T = double; };
 template <> struct Epi<true> { using T = float; };
 
+// The solve's matrix is the caller's CSR (rp_a, col_a, val_a) or its
+// relabelled copy (rp_b, ...), as the setup kernels decided.  Both come in as
+// kernel arguments, so the compiler knows them to be global memory and emits
+// global loads (pointers read from the state would give FLAT loads, which also
+// count against the LDS counter).
 template <int P, int NW, bool XCACHE, bool F = false>
 __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                        typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
                                                        int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
-                                                       uint32_t* tk, double* head, double* tail, double* part) {
+                                                       uint32_t* tk, double* head, double* tail, double* part,
+                                                       const int64_t* rp_a, const int32_t* col_a, const void* val_a,
+                                                       const int64_t* rp_b, const int32_t* col_b, const void* val_b) {
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
@@ -51,9 +58,10 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
             w[r] = (WT)(r < n ? u01(rs, (uint64_t)(perm ? perm[r] : r)) : 0.0);
         return;
     }
-    const int64_t* rp = st->crp;
-    const int32_t* col = st->ccol;
-    const VT* val = (const VT*)st->cval;
+    const bool rl = st->reordered != 0;
+    const int64_t* rp = rl ? rp_b : rp_a;
+    const int32_t* col = rl ? col_b : col_a;
+    const VT* val = (const VT*)(rl ? val_b : val_a);
     const VT* x = Vb + (int64_t)j * ld;
     const VT* xp = j > 0 ? Vb + (int64_t)(j - 1) * ld : nullptr;
     const E sj = (E)st->scale[j];
@@ -124,17 +132,19 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
     using WT = typename Tr<P>::W;
     if constexpr (P == 0) {
         hipLaunchKernelGGL((k_spmv_step<P, WAVES, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V,
-                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr, a.col, a.val,
+                           b.rp2, b.col2, b.val2);
     } else if (!p.xcache) {
         hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st,
                            (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                           b.part2);
+                           b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
     } else {
         // One workgroup of XW wavefronts per CU (its LDS holds the x head).
         const int64_t g = std::min<int64_t>(256, (p.n_tiles + XW - 1) / XW);
         const int gx = (int)((g + 7) / 8 * 8);
         hipLaunchKernelGGL((k_spmv_step<P, XW, true, F>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
-                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2);
+                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr, a.col, a.val,
+                           b.rp2, b.col2, b.val2);
     }
 }
 
