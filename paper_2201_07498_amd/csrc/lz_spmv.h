@@ -124,12 +124,16 @@ __device__ __forceinline__ double split_total(const double* head, const double* 
 }
 
 // NW wavefronts per workgroup.  With CACHED, xs holds x[0..hn) in LDS and
-// gathers of those entries read it instead of global memory.
+// gathers of those entries read it instead of global memory.  With OFF32
+// (every byte offset into x below 2^32), each load is a wave-uniform base in
+// scalar registers plus a 32-bit per-lane offset, and the col and val loads of
+// an entry share one offset; 64-bit per-lane addresses would otherwise take
+// about half of the kernel's vector registers and limit its occupancy.
 // The row bounds of the first 64 owned rows, pre() of those rows and the
 // start of the row continuing past the tile are loaded with the tile's
 // entries, so a tile waits for two rounds of requests (entries, then
 // gathers) before its sums are written.
-template <class VT, class AT, int NW, bool CACHED, class Pre, class Row, class Piece, class Fin>
+template <class VT, class AT, int NW, bool CACHED, bool OFF32, class Pre, class Row, class Piece, class Fin>
 __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const VT* __restrict__ x, const VT* xs,
                                            int hn, int64_t n, int64_t nnz, int64_t n_tiles,
@@ -172,17 +176,30 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
         if (cnt > 0) {
             int ci[TP];
             VT vv[TP];
+            if constexpr (OFF32) {
+                const char* cb = (const char*)(col + t0);
+                const char* vb = (const char*)(val + t0);
 #pragma unroll
-            for (int q = 0; q < TP; ++q) {
-                const int64_t p = t0 + min(q * 64 + lane, cnt - 1);
-                ci[q] = col[p];
-                vv[q] = val[p];
+                for (int q = 0; q < TP; ++q) {
+                    const uint32_t o = (uint32_t)min(q * 64 + lane, cnt - 1);
+                    ci[q] = *(const int32_t*)(cb + o * 4u);
+                    vv[q] = *(const VT*)(vb + o * (uint32_t)sizeof(VT));
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < TP; ++q) {
+                    const int64_t p = t0 + min(q * 64 + lane, cnt - 1);
+                    ci[q] = col[p];
+                    vv[q] = val[p];
+                }
             }
 #pragma unroll
             for (int q = 0; q < TP; ++q) {
                 VT xv;
                 if constexpr (CACHED)
                     xv = ci[q] < hn ? xs[ci[q]] : x[ci[q]];
+                else if constexpr (OFF32)
+                    xv = *(const VT*)((const char*)x + (uint32_t)ci[q] * (uint32_t)sizeof(VT));
                 else
                     xv = x[ci[q]];
                 pw[q * 64 + lane] = to_a(vv[q], AT(0)) * to_a(xv, AT(0));

@@ -31,7 +31,7 @@ template <> struct Epi<true> { using T = float; };
 // kernel arguments, so the compiler knows them to be global memory and emits
 // global loads (pointers read from the state would give FLAT loads, which also
 // count against the LDS counter).
-template <int P, int NW, bool XCACHE, bool F = false>
+template <int P, int NW, bool XCACHE, bool F = false, bool OFF32 = false>
 __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                        typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
                                                        int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
@@ -88,8 +88,8 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
         for (int i = threadIdx.x; i < hn; i += NW * 64) xs[i] = x[i];
         __syncthreads();
     }
-    spmv_tiles<VT, AT, NW, XCACHE>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, pre, row, piece,
-                                   fin);
+    spmv_tiles<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, pre, row,
+                                          piece, fin);
     if (!need_alpha) return;
     apart = block_sum(apart, shd, NW);
     if (threadIdx.x == 0) st_dev(&part[blockIdx.x], (double)apart);
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
     if (st->status != 0) return;
-    spmv_tiles<VT, AT, WAVES, false>(
+    spmv_tiles<VT, AT, WAVES, false, false>(
         rp, col, val, x, nullptr, 0, n, nnz, n_tiles, ob, tk, head, tail, [](int64_t) { return 0.0; },
         [&](int64_t r, double acc, double) { y[r] = (WT)acc; }, [&](int64_t, double) {},
         [&](int64_t r, double acc) { y[r] = (WT)acc; });
@@ -130,21 +130,28 @@ template <int P, bool F = false>
 static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
     using VT = typename Tr<P>::V;
     using WT = typename Tr<P>::W;
-    if constexpr (P == 0) {
-        hipLaunchKernelGGL((k_spmv_step<P, WAVES, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, (const VT*)b.V,
-                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr, a.col, a.val,
-                           b.rp2, b.col2, b.val2);
-    } else if (!p.xcache) {
-        hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st,
-                           (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                           b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
-    } else {
-        // One workgroup of XW wavefronts per CU (its LDS holds the x head).
-        const int64_t g = std::min<int64_t>(256, (p.n_tiles + XW - 1) / XW);
-        const int gx = (int)((g + 7) / 8 * 8);
-        hipLaunchKernelGGL((k_spmv_step<P, XW, true, F>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
-                           (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr, a.col, a.val,
-                           b.rp2, b.col2, b.val2);
+    // 32-bit byte offsets reach every entry of x.
+    const bool off32 = (uint64_t)p.n * sizeof(VT) <= (uint64_t(1) << 32);
+    if constexpr (P != 0) {
+        if (p.xcache) {
+            // One workgroup of XW wavefronts per CU (its LDS holds the x head).
+            const int64_t g = std::min<int64_t>(256, (p.n_tiles + XW - 1) / XW);
+            const int gx = (int)((g + 7) / 8 * 8);
+            hipLaunchKernelGGL((k_spmv_step<P, XW, true, F>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
+                               (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr,
+                               a.col, a.val, b.rp2, b.col2, b.val2);
+            return;
+        }
+    }
+    {
+        if (off32)
+            hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st,
+                               (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
+                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
+        else
+            hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st,
+                               (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
+                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
     }
 }
 
