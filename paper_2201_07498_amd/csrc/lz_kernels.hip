@@ -607,6 +607,9 @@ static hipError_t iteration_pa(const Plan& p, const Bufs& b, const Csr& a, int n
     using WT = typename Tr<P>::W;
     VT* V = (VT*)b.V;
     WT* w = (WT*)b.w;
+    // The final reductions of the orthogonalisation kernels read at most
+    // OGRID partial rows.
+    if (p.g_orth < 1 || p.g_orth > OGRID) return hipErrorInvalidValue;
     if (ev) (void)hipEventRecord(ev[0], s);
     launch_spmv_step(p, b, a, s);
     if (ev) (void)hipEventRecord(ev[1], s);
