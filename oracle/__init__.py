@@ -6,12 +6,12 @@ benchmark's CPU-baseline leg may import this package.  The product library
 
 The arithmetic lives in ``lanczos_oracle.c`` (plain sequential C, binary64);
 this module only marshals numpy arrays through ctypes and composes the
-steps in the order of Sec. II of the paper:
+steps in the order of Sec. III of the paper:
 
   1. Lanczos with full reorthogonalisation (Algorithm 1) -> alpha, beta, V
-  2. Jacobi on the tridiagonal T (Sec. II, second phase) -> theta, S
+  2. Jacobi on the tridiagonal T (Sec. III, second phase) -> theta, S
   3. Top-K by modulus (Sec. I)
-  4. Ritz vectors V S (Sec. II)
+  4. Ritz vectors V S (Sec. III)
   5. Accuracy report (Sec. IV-D): residuals, orthogonality, mean angle
 
 Matrix values are taken as float64 (values stored in a lower precision are

@@ -34,7 +34,7 @@
  *   - The start vector is u_r = U01(SplitMix64(seed, r)), v_1 = u/||u||;
  *     restart number k draws from seed + k * 2^32.
  *   - Jacobi is the cyclic-by-row method with Rutishauser's rotation
- *     (Sec. II cites Rutishauser's Jacobi method for the small problem).
+ *     (Sec. III cites Rutishauser's Jacobi method for the small problem).
  */
 #include <math.h>
 #include <stdint.h>
@@ -119,7 +119,7 @@ int orc_lanczos(int64_t n, const int64_t *rowptr, const int32_t *col,
     int restarts = 0;
     double tnorm = 0.0;      /* running max_j (|alpha_j| + beta_j) */
 
-    /* v_1: L2-normalised random vector (Sec. II, Algorithm 1 inputs). */
+    /* v_1: L2-normalised random vector (Sec. III, Algorithm 1 inputs). */
     double *v1 = V;
     for (int64_t r = 0; r < n; ++r) v1[r] = orc_u01(seed, (uint64_t)r);
     double s0 = nrm2(n, v1);
@@ -172,7 +172,7 @@ int orc_lanczos(int64_t n, const int64_t *rowptr, const int32_t *col,
 
 /*
  * Cyclic-by-row Jacobi eigensolver for a dense symmetric m x m matrix
- * (Sec. II, the second phase; Rutishauser's formulation).
+ * (Sec. III, the second phase; Rutishauser's formulation).
  *   A: row-major, overwritten; on return its diagonal holds the eigenvalues.
  *   S: row-major m x m; on return column k is the eigenvector of A_kk.
  * A rotation in plane (p,q) is skipped when |a_pq| is negligible against
@@ -257,7 +257,7 @@ void orc_select_topk(int m, const double *theta, int K, int *idx)
 }
 
 /*
- * Ritz vectors (Sec. II: the eigenvectors of M are the Lanczos basis times
+ * Ritz vectors (Sec. III: the eigenvectors of M are the Lanczos basis times
  * the eigenvectors of T).  Y[:,k] = sum_i V[:,i] * S[i, idx[k]], i < m,
  * then scaled to unit 2-norm and signed so that its entry of largest
  * modulus (lowest index on ties) is positive.  Y is n x K column-major.

@@ -1,4 +1,4 @@
-// gfx950 kernels of one Lanczos iteration (Sec. II, Algorithm 1) and the
+// gfx950 kernels of one Lanczos iteration (Sec. III, Algorithm 1) and the
 // start vector.
 //
 // One iteration is three kernels:

@@ -1,7 +1,7 @@
 """Pins for the FP64 CPU oracle, against facts that do not come from the
 oracle itself: published generator outputs, dense LAPACK eigensolves,
 closed-form graph spectra, extended-precision Krylov projections, ARPACK and
-the algebraic invariants of the Lanczos relation (Sec. II, Algorithm 1).
+the algebraic invariants of the Lanczos relation (Sec. III, Algorithm 1).
 
 The paper prints no eigenvalues or worked example, so every pin here is
 mathematical or from an independent library routine.
