@@ -5,12 +5,13 @@
  *
  * Method: Sgherzi, Parravicini, Santambrogio, "A Mixed Precision, Multi-GPU
  * Design for Large-scale Top-K Sparse Eigenproblems" (2022).
- *   Sec. II, Algorithm 1   Lanczos iteration (SpMV, alpha, three-term update,
- *                          orthogonalisation, beta, normalisation)
- *   Sec. II (2nd phase)    Jacobi on the tridiagonal T, Ritz vectors V*S
- *   Sec. I                 Top-K = the K eigenvalues largest in modulus
- *   Sec. II-A              storage vs. computation precision (FDF)
- *   Sec. IV-D              accuracy metrics: L2 residual, pairwise angle
+ *   Sec. III, Algorithm 1   Lanczos iteration (SpMV, alpha, three-term update,
+ *                           orthogonalisation, beta, normalisation)
+ *   Sec. III (2nd phase)    Jacobi on the tridiagonal T, Ritz vectors V*S
+ *   Sec. I                  Top-K = the K eigenvalues largest in modulus
+ *   Sec. III-A              storage vs. computation precision (FDF)
+ *   Sec. III-B, IV-B        out-of-core matrices (host-resident mode)
+ *   Sec. IV-D               accuracy metrics: L2 residual, pairwise angle
  *
  * Conventions shared by every entry point:
  *   - Return value is an lz_status code; it is the only error channel.
@@ -37,7 +38,7 @@ extern "C" {
 
 #define LZ_MAX_STEPS 64
 
-/* Storage precision of the matrix values and the Lanczos basis (Sec. II-A).
+/* Storage precision of the matrix values and the Lanczos basis (Sec. III-A).
  * LZ_FP64: values, basis and SpMV accumulation in binary64.
  * LZ_FP32: values and basis stored binary32, SpMV accumulates in binary32.
  * LZ_BF16: values and basis stored bfloat16, SpMV accumulates in binary32.
@@ -138,6 +139,10 @@ typedef struct lz_report {
     double t_finish_ms;      /* Jacobi, selection, Ritz vectors, report */
     int32_t reordered;       /* 1: the solve ran on the hub-first relabelling */
     int32_t pad;
+    int64_t bytes_streamed;  /* lanczos_topk_host: host-to-device bytes of
+                                matrix entries (column indices and values)
+                                copied during the solve, the one copy of the
+                                resident slabs included; 0 otherwise */
 } lz_report;
 
 /* Fills *opt with the defaults above. */
@@ -147,7 +152,7 @@ void lz_options_init(lz_options* opt);
 const char* lz_status_string(int status);
 
 /*
- * Top-K eigenpairs of the symmetric CSR matrix (Sec. II, Algorithm 1 then
+ * Top-K eigenpairs of the symmetric CSR matrix (Sec. III, Algorithm 1 then
  * Jacobi and the Ritz product), the K eigenvalues of largest modulus.
  *   out_vals: device double[K], ordered by |lambda| descending, ties by
  *             lambda descending.
@@ -175,6 +180,50 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
                     const lz_options* opt, lz_report* report);
 
 /*
+ * lanczos_topk_ex on a matrix whose entries stay in host memory, for matrices
+ * larger than device memory (the paper's out-of-core matrices: Sec. III-B
+ * runs them through unified memory, Sec. IV-B measures them).
+ *   host_rowptr: host int64[n+1] (any host memory); nnz = host_rowptr[n].
+ *                Copied to the device once (8(n+1) bytes).
+ *   host_col, host_val: host arrays of nnz entries in PINNED memory
+ *                (hipHostMalloc or an equivalent page-locked allocation;
+ *                anything else returns LZ_ERR_INVALID_ARG).  They are read
+ *                by DMA while kernels run and must not change until the
+ *                call returns.
+ *   slab_nnz:    entries per streamed slab; 0 selects
+ *                LZ_HOST_SLAB_NNZ_DEFAULT.  Slabs are runs of whole SpMV
+ *                tiles of at most slab_nnz entries; two staging buffers of
+ *                that size are allocated.  Must be >= 2048 and leave at most
+ *                LZ_HOST_MAX_SLABS slabs.
+ *   resident_nnz: leading entries (whole slabs) that stay on the device
+ *                after one copy; 0 streams every slab at every pass,
+ *                >= nnz keeps the whole matrix resident.
+ * Every SpMV, and the residual product of the report, streams the
+ * non-resident slabs from host memory on a copy stream of the call's own,
+ * overlapped with the kernels of earlier slabs.  Column indices are checked
+ * on the device in the first pass, before any kernel gathers through them.
+ * The solve runs in the caller's row order: opt->reorder = LZ_REORDER_HUBS
+ * returns LZ_ERR_INVALID_ARG and LZ_REORDER_AUTO does not relabel.  Results
+ * equal lanczos_topk_ex with LZ_REORDER_OFF bit for bit in the modes whose
+ * alpha comes from the orthogonalisation (LZ_REORTH_TWICE, _SELECTIVE);
+ * with LZ_REORTH_NONE and _ONCE the alpha partial sums are grouped by slab.
+ * opt->workspace (lanczos_topk_host_workspace_size bytes) covers the solve
+ * state; the staging and resident buffers are allocated by the call and
+ * freed before it returns.  report->bytes_streamed counts the copies.
+ * Blocking.
+ */
+#define LZ_HOST_SLAB_NNZ_DEFAULT (int64_t)(1 << 24)
+#define LZ_HOST_MAX_SLABS 16384
+int lanczos_topk_host(const int64_t* host_rowptr, const int32_t* host_col, const void* host_val,
+                      int64_t n, int32_t K, int32_t m, int32_t precision, int64_t slab_nnz,
+                      int64_t resident_nnz, void* stream, double* out_vals, double* out_vecs,
+                      const lz_options* opt, lz_report* report);
+
+/* Device bytes of the workspace of lanczos_topk_host (no relabelled copy). */
+size_t lanczos_topk_host_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m,
+                                        int32_t precision);
+
+/*
  * y = A x in the given precision (Algorithm 1, the SpMV line), with the
  * same row partitioning and kernels the solver uses.  x and y are device
  * arrays of n elements of the storage type (y is double for LZ_FP64, float
@@ -185,7 +234,7 @@ int lz_spmv(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_v
 
 /*
  * Eigen-decomposition of one symmetric tridiagonal matrix by the parallel
- * Jacobi kernel the solver uses (Sec. II, second phase).  Host arrays:
+ * Jacobi kernel the solver uses (Sec. III, second phase).  Host arrays:
  * alpha[m] diagonal, offdiag[m-1]; out theta[m] (unsorted, Jacobi order),
  * S[m*m] row-major, column k = eigenvector of theta[k].  m <= LZ_MAX_STEPS.
  * Returns LZ_ERR_NOT_CONVERGED if the sweep limit was hit.  Blocking.

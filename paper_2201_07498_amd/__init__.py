@@ -47,7 +47,8 @@ class Report(ctypes.Structure):
                 ("beta", ctypes.c_double * (MAX_STEPS + 1)), ("theta", ctypes.c_double * MAX_STEPS),
                 ("t_setup_ms", ctypes.c_double), ("t_lanczos_ms", ctypes.c_double),
                 ("t_spmv_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double),
-                ("t_finish_ms", ctypes.c_double), ("reordered", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("t_finish_ms", ctypes.c_double), ("reordered", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("bytes_streamed", ctypes.c_int64)]
 
     def to_dict(self, K: int, m: int) -> dict:
         return dict(status=self.status, m_eff=self.m_eff, restarts=self.restarts,
@@ -58,7 +59,7 @@ class Report(ctypes.Structure):
                     beta=np.array(self.beta[:m + 1]), theta=np.array(self.theta[:m]),
                     t_setup_ms=self.t_setup_ms, t_lanczos_ms=self.t_lanczos_ms,
                     t_spmv_ms=self.t_spmv_ms, t_orth_ms=self.t_orth_ms, t_finish_ms=self.t_finish_ms,
-                    reordered=bool(self.reordered))
+                    reordered=bool(self.reordered), bytes_streamed=int(self.bytes_streamed))
 
 
 _lib = None
@@ -83,6 +84,11 @@ def lib() -> ctypes.CDLL:
         L.lanczos_topk_ex.restype = ctypes.c_int
         L.lanczos_topk_ex.argtypes = [P, P, P, i64, i64, i32, i32, i32, P, P, P,
                                       ctypes.POINTER(Options), ctypes.POINTER(Report)]
+        L.lanczos_topk_host.restype = ctypes.c_int
+        L.lanczos_topk_host.argtypes = [P, P, P, i64, i32, i32, i32, i64, i64, P, P, P,
+                                        ctypes.POINTER(Options), ctypes.POINTER(Report)]
+        L.lanczos_topk_host_workspace_size.restype = ctypes.c_size_t
+        L.lanczos_topk_host_workspace_size.argtypes = [i64, i64, i32, i32, i32]
         L.lz_spmv.restype = ctypes.c_int
         L.lz_spmv.argtypes = [P, P, P, i64, i64, i32, P, P, P]
         L.lz_ortho_loss.restype = ctypes.c_int
@@ -153,6 +159,49 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
                                ctypes.byref(opt), ctypes.byref(rep))
     if rc != 0:
         raise LanczosError(rc, "lanczos_topk_ex")
+    return vals, vecs.T, rep.to_dict(K, m)
+
+
+def host_workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
+    return int(lib().lanczos_topk_host_workspace_size(n, nnz, K, m, _prec(precision)))
+
+
+def topk_host(rowptr, col, val, K: int, m: int, precision="fp64", slab_nnz: int = 0, resident_nnz: int = 0,
+              seed: int = 0, reorth="twice", report: bool = True, stream=None, workspace=None,
+              profile: bool = False, out=None, arith="mixed", device="cuda:0"):
+    """Top-K eigenpairs of a matrix whose entries stay in host memory
+    (lanczos_topk_host).  rowptr: contiguous int64 CPU tensor; col, val:
+    contiguous pinned CPU tensors (int32, and the storage dtype).  Results are
+    device tensors as in topk()."""
+    import torch
+    p = _prec(precision)
+    want = {LZ_FP64: torch.float64, LZ_FP32: torch.float32, LZ_BF16: torch.bfloat16}[p]
+    for t, dt, name in ((rowptr, torch.int64, "rowptr"), (col, torch.int32, "col"), (val, want, "val")):
+        if t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {dt} host tensor")
+    n = rowptr.numel() - 1
+    if out is None:
+        vals = torch.empty(K, dtype=torch.float64, device=device)
+        vecs = torch.empty(K, n, dtype=torch.float64, device=device)
+    else:
+        vals, vecs = out
+    opt = Options()
+    lib().lz_options_init(ctypes.byref(opt))
+    opt.seed = seed & (2 ** 64 - 1)
+    opt.reorth = REORTH[reorth] if isinstance(reorth, str) else int(reorth)
+    opt.report = 1 if report else 0
+    opt.profile = 1 if profile else 0
+    opt.reorder = REORDER["off"]
+    opt.arith = ARITH[arith] if isinstance(arith, str) else int(arith)
+    if workspace is not None:
+        opt.workspace = ctypes.c_void_p(workspace.data_ptr())
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    rep = Report()
+    rc = lib().lanczos_topk_host(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, K, m, p, slab_nnz,
+                                 resident_nnz, _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(),
+                                 ctypes.byref(opt), ctypes.byref(rep))
+    if rc != 0:
+        raise LanczosError(rc, "lanczos_topk_host")
     return vals, vecs.T, rep.to_dict(K, m)
 
 

@@ -6,6 +6,7 @@
 
 #include "../../include/lanczos_topk.h"
 #include "lz_internal.h"
+#include "lz_ooc.h"
 
 namespace lz {
 
@@ -17,7 +18,7 @@ static int pow2_ge(int k) {
     return v;
 }
 
-Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
+Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool relabel) {
     Plan p;
     p.n = n;
     p.nnz = nnz;
@@ -60,10 +61,10 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec) {
     p.off_head = take((size_t)p.n_tiles * kb2 * 8);
     p.off_tail = take((size_t)p.n_tiles * kb2 * 8);
     p.off_rp2 = take((size_t)(n + 1) * 8);
-    p.off_col2 = take((size_t)nnz * 4);
-    p.off_val2 = take((size_t)nnz * vb);
-    p.off_perm = take((size_t)n * 4);
-    p.off_iperm = take((size_t)n * 4);
+    p.off_col2 = take(relabel ? (size_t)nnz * 4 : 0);
+    p.off_val2 = take(relabel ? (size_t)nnz * vb : 0);
+    p.off_perm = take(relabel ? (size_t)n * 4 : 0);
+    p.off_iperm = take(relabel ? (size_t)n * 4 : 0);
     p.off_gm = take((size_t)NCMAX * NCMAX * 8);
     p.bytes = o;
     return p;
@@ -114,56 +115,27 @@ static int check_common(const void* rowptr, const void* col, const void* val, in
     return LZ_OK;
 }
 
-extern "C" {
-
-void lz_options_init(lz_options* opt) {
-    if (!opt) return;
-    std::memset(opt, 0, sizeof(*opt));
-    opt->seed = 0;
-    opt->reorth = LZ_REORTH_TWICE;
-    opt->report = 1;
-    opt->reorder = LZ_REORDER_AUTO;
-}
-
-const char* lz_status_string(int status) {
-    switch (status) {
-        case LZ_OK: return "ok";
-        case LZ_ERR_INVALID_ARG: return "invalid argument";
-        case LZ_ERR_OUT_OF_MEMORY: return "out of device memory";
-        case LZ_ERR_HIP: return "HIP runtime error";
-        case LZ_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
-        case LZ_ERR_TOO_LARGE: return "request larger than the memory budget";
-        case LZ_ERR_NOT_CONVERGED: return "Jacobi did not converge";
-        case LZ_ERR_NONFINITE: return "non-finite value in the Lanczos recurrence";
-        case LZ_ERR_BREAKDOWN: return "restart vector lies in the Krylov basis";
-        case LZ_PENDING: return "pending";
-        default: return "unknown status";
-    }
-}
-
-size_t lanczos_topk_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision) {
-    if (n < 1 || nnz < 0 || K < 1 || m < K || m > LZ_MAX_STEPS || precision < 0 || precision > 2) return 0;
-    return make_plan(n, nnz, K, m, precision).bytes;
-}
-
-int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n, int64_t nnz,
-                    int32_t K, int32_t m, int32_t precision, void* stream, double* out_vals, double* out_vecs,
-                    const lz_options* opt, lz_report* report) {
-    int rc = check_common(csr_rowptr, csr_col, csr_val, n, K, m, precision);
-    if (rc != LZ_OK) return rc;
-    if (!out_vals || !out_vecs || nnz < 0 || nnz >= (int64_t(1) << 40)) return LZ_ERR_INVALID_ARG;
-    lz_options o;
-    lz_options_init(&o);
-    if (opt) o = *opt;
+static int check_options(const lz_options* opt, int32_t precision, lz_options* out) {
+    lz_options_init(out);
+    if (opt) *out = *opt;
+    const lz_options& o = *out;
     if (o.reorth < LZ_REORTH_NONE || o.reorth > LZ_REORTH_SELECTIVE) return LZ_ERR_INVALID_ARG;
     if (o.reorder < LZ_REORDER_OFF || o.reorder > LZ_REORDER_AUTO) return LZ_ERR_INVALID_ARG;
     if (o.arith < LZ_ARITH_MIXED || o.arith > LZ_ARITH_FP32) return LZ_ERR_INVALID_ARG;
     if (o.arith == LZ_ARITH_FP32 && precision != LZ_FP32) return LZ_ERR_INVALID_ARG;
-    Plan p = make_plan(n, nnz, K, m, precision);
-    p.fff = o.arith == LZ_ARITH_FP32;
-    if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
+    return LZ_OK;
+}
 
-    hipStream_t s = (hipStream_t)stream;
+namespace lz {
+
+// The launch sequence of one solve, shared by the device-resident and the
+// host-resident entry points (arguments already checked).  With hc, the
+// matrix entries stay in host memory and a.rowptr is a host array.
+int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_vals, double* out_vecs,
+              lz_report* report, HostCsr* hc) {
+    const int64_t n = a.n;
+    const int32_t K = p.K, m = p.m;
+    int rc = LZ_OK;
     void* ws = o.workspace;
     bool owned = false;
     State* hst = nullptr;
@@ -192,7 +164,6 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             owned = true;
         }
         const Bufs b = resolve(p, ws);
-        const Csr a{csr_rowptr, csr_col, csr_val, n, nnz};
         // Pinned host copy of the state (one per host thread, kept for the
         // process): pageable copies are staged in many small blits.
         static thread_local State* pinned = nullptr;
@@ -206,8 +177,22 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             for (int i = 0; i < 5; ++i) LZ_HIP(hipEventCreate(&pev[i]));
             LZ_HIP(hipEventRecord(pev[0], s));
         }
-        LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, o.reorder, s));
-        if (o.reorder != LZ_REORDER_OFF && want_xcache(p, true)) {
+        if (hc) {
+            // Row pointers to the device (the slot of the relabelled ones).
+            LZ_HIP(hipMemcpyAsync(b.rp2, a.rowptr, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
+            a.rowptr = b.rp2;
+        }
+        LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, hc ? LZ_REORDER_OFF : o.reorder, s));
+        if (hc) {
+            const hipError_t pe = ooc_prepare(p, b, hc->ooc, hc->slab_nnz, hc->resident_nnz, s);
+            if (pe == hipErrorOutOfMemory) {
+                rc = LZ_ERR_OUT_OF_MEMORY;
+                goto done;
+            }
+            LZ_HIP(pe);
+            p.ooc = &hc->ooc;
+        }
+        if (!hc && o.reorder != LZ_REORDER_OFF && want_xcache(p, true)) {
             // The SpMV variant depends on the row order the device chose.
             LZ_HIP(hipMemcpyAsync(hst, b.st, offsetof(State, maxdeg), hipMemcpyDeviceToHost, s));
             LZ_HIP(hipStreamSynchronize(s));
@@ -259,6 +244,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
             report->ritz_ortho_loss = hst->ritz_ortho_loss;
             report->mean_angle_deg = hst->mean_angle_deg;
             report->reordered = hst->reordered;
+            report->bytes_streamed = hc ? hc->ooc.streamed : 0;
             if (o.profile && launched > 0) {
                 float ms = 0.f;
                 double sp = 0.0;
@@ -278,14 +264,108 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
         }
     }
 done:
-    if (owned) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(ws);
-    }
+    if (owned || hc) (void)hipStreamSynchronize(s);
+    if (hc) ooc_release(hc->ooc);
+    if (owned) (void)hipFree(ws);
     for (hipEvent_t e : iev) (void)hipEventDestroy(e);
     for (hipEvent_t e : pev)
         if (e) (void)hipEventDestroy(e);
     return rc;
+}
+
+}  // namespace lz
+
+extern "C" {
+
+void lz_options_init(lz_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->seed = 0;
+    opt->reorth = LZ_REORTH_TWICE;
+    opt->report = 1;
+    opt->reorder = LZ_REORDER_AUTO;
+}
+
+const char* lz_status_string(int status) {
+    switch (status) {
+        case LZ_OK: return "ok";
+        case LZ_ERR_INVALID_ARG: return "invalid argument";
+        case LZ_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case LZ_ERR_HIP: return "HIP runtime error";
+        case LZ_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case LZ_ERR_TOO_LARGE: return "request larger than the memory budget";
+        case LZ_ERR_NOT_CONVERGED: return "Jacobi did not converge";
+        case LZ_ERR_NONFINITE: return "non-finite value in the Lanczos recurrence";
+        case LZ_ERR_BREAKDOWN: return "restart vector lies in the Krylov basis";
+        case LZ_PENDING: return "pending";
+        default: return "unknown status";
+    }
+}
+
+size_t lanczos_topk_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision) {
+    if (n < 1 || nnz < 0 || K < 1 || m < K || m > LZ_MAX_STEPS || precision < 0 || precision > 2) return 0;
+    return make_plan(n, nnz, K, m, precision).bytes;
+}
+
+int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n, int64_t nnz,
+                    int32_t K, int32_t m, int32_t precision, void* stream, double* out_vals, double* out_vecs,
+                    const lz_options* opt, lz_report* report) {
+    int rc = check_common(csr_rowptr, csr_col, csr_val, n, K, m, precision);
+    if (rc != LZ_OK) return rc;
+    if (!out_vals || !out_vecs || nnz < 0 || nnz >= (int64_t(1) << 40)) return LZ_ERR_INVALID_ARG;
+    lz_options o;
+    rc = check_options(opt, precision, &o);
+    if (rc != LZ_OK) return rc;
+    Plan p = make_plan(n, nnz, K, m, precision);
+    p.fff = o.arith == LZ_ARITH_FP32;
+    if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
+    return run_solve(p, Csr{csr_rowptr, csr_col, csr_val, n, nnz}, o, (hipStream_t)stream, out_vals, out_vecs,
+                     report, nullptr);
+}
+
+size_t lanczos_topk_host_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision) {
+    if (n < 1 || nnz < 0 || K < 1 || m < K || m > LZ_MAX_STEPS || precision < 0 || precision > 2) return 0;
+    return make_plan(n, nnz, K, m, precision, false).bytes;
+}
+
+int lanczos_topk_host(const int64_t* host_rowptr, const int32_t* host_col, const void* host_val, int64_t n,
+                      int32_t K, int32_t m, int32_t precision, int64_t slab_nnz, int64_t resident_nnz, void* stream,
+                      double* out_vals, double* out_vecs, const lz_options* opt, lz_report* report) {
+    int rc = check_common(host_rowptr, host_col, host_val, n, K, m, precision);
+    if (rc != LZ_OK) return rc;
+    if (!out_vals || !out_vecs || resident_nnz < 0) return LZ_ERR_INVALID_ARG;
+    const int64_t nnz = host_rowptr[n];
+    if (host_rowptr[0] != 0 || nnz < 0 || nnz >= (int64_t(1) << 40)) return LZ_ERR_INVALID_ARG;
+    if (slab_nnz == 0) slab_nnz = LZ_HOST_SLAB_NNZ_DEFAULT;
+    // Every slab but the last holds more than slab_nnz - TILE entries.
+    if (slab_nnz < 2 * TILE || nnz / (slab_nnz - TILE) + 2 > LZ_HOST_MAX_SLABS) return LZ_ERR_INVALID_ARG;
+    lz_options o;
+    rc = check_options(opt, precision, &o);
+    if (rc != LZ_OK) return rc;
+    if (o.reorder == LZ_REORDER_HUBS) return LZ_ERR_INVALID_ARG;
+    Plan p = make_plan(n, nnz, K, m, precision, false);
+    p.fff = o.arith == LZ_ARITH_FP32;
+    if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
+    // The entries are copied asynchronously while kernels run: they must be
+    // pinned (page-locked) host memory.
+    auto pinned_host = [](const void* ptr) {
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return at.type == hipMemoryTypeHost;
+    };
+    if (!pinned_host(host_col) || !pinned_host(host_val)) return LZ_ERR_INVALID_ARG;
+    HostCsr hc;
+    hc.slab_nnz = slab_nnz;
+    hc.resident_nnz = resident_nnz;
+    hc.ooc.hcol = host_col;
+    hc.ooc.hval = (const char*)host_val;
+    hc.ooc.vb = storage_bytes(precision);
+    hc.ooc.n = n;
+    return run_solve(p, Csr{host_rowptr, nullptr, nullptr, n, nnz}, o, (hipStream_t)stream, out_vals, out_vecs,
+                     report, &hc);
 }
 
 int lanczos_topk(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n, int32_t K,

@@ -1,10 +1,11 @@
-// gfx950 kernels after the Lanczos loop (Sec. II, second phase): Jacobi on
+// gfx950 kernels after the Lanczos loop (Sec. III, second phase): Jacobi on
 // the tridiagonal T, Top-K selection, Ritz vectors, and the accuracy report
 // of Sec. IV-D (residuals, orthogonality of the basis and of the Ritz
 // vectors, mean pairwise angle).
 #include <algorithm>
 #include <cmath>
 
+#include "lz_ooc.h"
 #include "lz_spmv.h"
 
 namespace lz {
@@ -403,7 +404,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
                                                 int64_t n, int64_t nnz, int64_t n_tiles, const int32_t* __restrict__ ob,
                                                 uint32_t* tk, double* head, double* tail, int KB2,
                                                 const int64_t* rp_a, const int32_t* col_a, const void* val_a,
-                                                const int64_t* rp_b, const int32_t* col_b, const void* val_b) {
+                                                const int64_t* rp_b, const int32_t* col_b, const void* val_b,
+                                                int64_t tb, int64_t te) {
     using VT = typename Tr<P>::V;
     __shared__ int scol_all[WAVES][TILE];
     __shared__ VT sval_all[WAVES][TILE];
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
         z = group_sum(z, KB2);
         return act ? z + ld_dev(&head[t2 * KB2 + k]) : 0.0;
     };
-    const TileRange tr = wave_tiles(n_tiles);
+    const TileRange tr = wave_tiles(tb, te);
     for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
         const int64_t r_lo = ob[t], r_hi = ob[t + 1];
         const int64_t t0 = t * TILE - r_lo;
@@ -748,9 +750,21 @@ static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* o
     const int kb2 = pow2_at_least(p.K);
     const int gc = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p.n * kb2 + 4 * BLOCK - 1) / (4 * BLOCK)));
     hipLaunchKernelGGL(k_colstats, dim3(gc), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, b.part);
-    if (report)
+    if (report && p.ooc) {
+        // Host-resident matrix: the residual product streams the slabs too.
+        const hipError_t e = ooc_pass(*p.ooc, b.st, s,
+                                      [&](const int32_t* col, const void* val, int64_t tb, int64_t te, int, int) {
+                                          hipLaunchKernelGGL((k_spmm<P>), dim3(p.g_slab), dim3(BLOCK), 0, s, b.st,
+                                                             b.Y, b.Z, p.n, p.nnz, p.n_tiles, b.ob, b.tk, b.head,
+                                                             b.tail, kb2, a.rowptr, col, val, nullptr, nullptr,
+                                                             nullptr, tb, te);
+                                      });
+        if (e != hipSuccess) return e;
+    } else if (report) {
         hipLaunchKernelGGL((k_spmm<P>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st, b.Y, b.Z, p.n, p.nnz, p.n_tiles,
-                           b.ob, b.tk, b.head, b.tail, kb2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
+                           b.ob, b.tk, b.head, b.tail, kb2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2,
+                           (int64_t)0, p.n_tiles);
+    }
     const int go = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (p.n + 63) / 64));
     hipLaunchKernelGGL(k_out, dim3(go), dim3(BLOCK), 0, s, b.st, b.Y, p.n, kb2, out_vecs);
     if (!report) return hipGetLastError();

@@ -71,6 +71,8 @@ constexpr size_t STATE_HEAD_BYTES = 64;
 constexpr size_t STATE_REPORT_BYTES = offsetof(State, S);
 static_assert(offsetof(State, status) + sizeof(int32_t) <= STATE_HEAD_BYTES, "state header");
 
+struct Ooc;   // host-resident matrix streamed in slabs (lz_ooc.h)
+
 // Workspace layout of one solve.  All offsets are in bytes from the base.
 struct Plan {
     int64_t n = 0, nnz = 0, ld = 0;
@@ -78,6 +80,8 @@ struct Plan {
     int32_t g_orth = 0, g_dense = 0, g_tile = 0;
     int32_t xcache = 0;         // Lanczos-step SpMV keeps the head of x in LDS (set once the row order is known)
     int32_t fff = 0;            // all-FP32 arithmetic (FP32 storage only): float instantiations
+    int32_t g_slab = 0;         // grid of the per-slab launches of a host-resident matrix
+    Ooc* ooc = nullptr;         // non-null: the matrix entries stay in host memory
     int64_t n_tiles = 0;
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
            off_Y = 0, off_Z = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0, off_tail = 0, off_rp2 = 0,
@@ -94,7 +98,10 @@ inline double unit_roundoff(int prec) {
 // in both mixed modes.
 inline double work_roundoff(int prec) { return prec == 0 ? 1.1102230246251565e-16 : 5.9604644775390625e-08; }
 
-Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec);
+// `relabel`: reserve the hub-first relabelled copy of the matrix (without it
+// the row-pointer slot still holds n + 1 entries, the device copy of the row
+// pointers of a host-resident matrix).
+Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool relabel = true);
 
 // Device pointers of a solve, resolved from a plan and a workspace base.
 struct Bufs {
@@ -140,7 +147,10 @@ hipError_t launch_init(const Plan& p, const Bufs& b, hipStream_t s);
 hipError_t launch_iteration(const Plan& p, const Bufs& b, const Csr& a, int ncols_bound, int reorth,
                             hipStream_t s, hipEvent_t* ev = nullptr);
 // The Lanczos-step SpMV of the current iteration (or its restart draw).
-void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s);
+hipError_t launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s);
+// Column checks 0 <= col[e] < n of entries [e0, e1) (col indexed by matrix
+// entry); a failure sets the solve status to LZ_ERR_INVALID_ARG.
+void launch_validate_cols(State* st, const int32_t* col, int64_t e0, int64_t e1, int64_t n, hipStream_t s);
 // The LDS copy of the head of x pays off for relabelled (power-law)
 // matrices in the mixed modes and costs occupancy elsewhere.  Measured on
 // MI355X: R-MAT scale 23 FP32 1.79 -> 1.59 ms, BF16 1.63 -> 1.25 ms; scale

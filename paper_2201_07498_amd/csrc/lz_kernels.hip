@@ -611,7 +611,8 @@ static hipError_t iteration_pa(const Plan& p, const Bufs& b, const Csr& a, int n
     // OGRID partial rows.
     if (p.g_orth < 1 || p.g_orth > OGRID) return hipErrorInvalidValue;
     if (ev) (void)hipEventRecord(ev[0], s);
-    launch_spmv_step(p, b, a, s);
+    const hipError_t es = launch_spmv_step(p, b, a, s);
+    if (es != hipSuccess) return es;
     if (ev) (void)hipEventRecord(ev[1], s);
     const int nb = nc_bucket(ncols);
 #define LZ_ORTH_CASE(NCV)                                                                                  \

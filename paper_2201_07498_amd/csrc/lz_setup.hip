@@ -49,7 +49,8 @@ __global__ void k_reset(State* st, int m, int K, int reorth, int reorder, double
 
 // Input checks before any kernel indexes memory through the CSR arrays:
 // rowptr[0] = 0, rowptr[n] = nnz, rows non-decreasing, 0 <= col < n.  Also
-// finds the longest row.
+// finds the longest row.  With col null (entries in host memory) only the
+// row pointers are checked here; k_validate_cols checks each slab.
 __global__ __launch_bounds__(BLOCK) void k_validate(State* st, const int64_t* rp, const int32_t* col, int64_t n,
                                                     int64_t nnz) {
     bool bad = false;
@@ -62,7 +63,8 @@ __global__ __launch_bounds__(BLOCK) void k_validate(State* st, const int64_t* rp
         bad |= d < 0;
         mx = d > 0 && (uint64_t)d > mx ? (uint64_t)d : mx;
     }
-    for (int64_t p = t0; p < nnz; p += stride) bad |= (col[p] < 0) || ((int64_t)col[p] >= n);
+    if (col)
+        for (int64_t p = t0; p < nnz; p += stride) bad |= (col[p] < 0) || ((int64_t)col[p] >= n);
     if (bad) __hip_atomic_store(&st->status, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // One atomic per workgroup (the grid is capped, so contention is small).
     __shared__ uint64_t smx[BLOCK / 64];
@@ -79,6 +81,23 @@ __global__ __launch_bounds__(BLOCK) void k_validate(State* st, const int64_t* rp
             __hip_atomic_fetch_max(&st->maxdeg, (unsigned long long)mx, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// Column checks of the entries [e0, e1) of a slab (col indexed by matrix
+// entry), before any kernel gathers through them.
+__global__ __launch_bounds__(BLOCK) void k_validate_cols(State* st, const int32_t* col, int64_t e0, int64_t e1,
+                                                         int64_t n) {
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t p = e0 + (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < e1; p += stride)
+        bad |= (col[p] < 0) || ((int64_t)col[p] >= n);
+    if (bad) __hip_atomic_store(&st->status, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+void launch_validate_cols(State* st, const int32_t* col, int64_t e0, int64_t e1, int64_t n, hipStream_t s) {
+    if (e1 <= e0) return;
+    const int g = (int)std::min<int64_t>((e1 - e0 + BLOCK - 1) / BLOCK, 1024);
+    hipLaunchKernelGGL(k_validate_cols, dim3(g), dim3(BLOCK), 0, s, st, col, e0, e1, n);
 }
 
 // Chooses the matrix of the solve and publishes its pointers in the state.
@@ -284,7 +303,7 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
     const int lane = threadIdx.x & 63;
     int64_t* s = srp[threadIdx.x >> 6];
     int64_t* d = sdel[threadIdx.x >> 6];
-    const TileRange tr = wave_tiles<FILL_WAVES>(n_tiles);
+    const TileRange tr = wave_tiles<FILL_WAVES>(0, n_tiles);
     for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
         const int64_t r_lo = ob[t], r_hi = ob[t + 1];
         const int64_t t0 = t * TILE - r_lo;

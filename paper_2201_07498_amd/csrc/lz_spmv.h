@@ -96,16 +96,18 @@ __device__ __forceinline__ AT lds_wave_sum(const AT* p, int b, int e, int lane) 
     return wave_sum(s);
 }
 
-// Tiles handled by this wavefront: the tile range is split evenly over the
-// eight XCDs (workgroup i runs on XCD i mod 8), so neighbouring tiles, which
-// gather neighbouring parts of x in a banded matrix, share one L2.
+// Tiles handled by this wavefront out of tiles [tb, te) (all tiles, or one
+// slab of a host-resident matrix): the range is split evenly over the eight
+// XCDs (workgroup i runs on XCD i mod 8), so neighbouring tiles, which gather
+// neighbouring parts of x in a banded matrix, share one L2.
 struct TileRange {
     int64_t first, end, stride;
 };
 template <int NW = WAVES>
-__device__ __forceinline__ TileRange wave_tiles(int64_t n_tiles) {
+__device__ __forceinline__ TileRange wave_tiles(int64_t tb, int64_t te) {
     const int64_t xcd = blockIdx.x & 7, nb8 = gridDim.x >> 3;
-    const int64_t lo = n_tiles * xcd / 8, hi = n_tiles * (xcd + 1) / 8;
+    const int64_t nt = te - tb;
+    const int64_t lo = tb + nt * xcd / 8, hi = tb + nt * (xcd + 1) / 8;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t w = (int64_t)(blockIdx.x >> 3) * NW + wave;
     return {lo + w, hi, nb8 * NW};
@@ -123,8 +125,10 @@ __device__ __forceinline__ double split_total(const double* head, const double* 
     return s + ld_dev(&head[t2]);
 }
 
-// NW wavefronts per workgroup.  With CACHED, xs holds x[0..hn) in LDS and
-// gathers of those entries read it instead of global memory.  With OFF32
+// NW wavefronts per workgroup; the grid walks tiles [tb, te) (tile indices
+// and the tables stay those of the whole matrix).  With CACHED, xs holds
+// x[0..hn) in LDS and gathers of those entries read it instead of global
+// memory.  With OFF32
 // (every byte offset into x below 2^32), each load is a wave-uniform base in
 // scalar registers plus a 32-bit per-lane offset, and the col and val loads of
 // an entry share one offset; 64-bit per-lane addresses would otherwise take
@@ -136,13 +140,13 @@ __device__ __forceinline__ double split_total(const double* head, const double* 
 template <class VT, class AT, int NW, bool CACHED, bool OFF32, class Pre, class Row, class Piece, class Fin>
 __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const VT* __restrict__ x, const VT* xs,
-                                           int hn, int64_t n, int64_t nnz, int64_t n_tiles,
-                                           const int32_t* __restrict__ ob, uint32_t* tk, double* head, double* tail,
-                                           Pre&& pre, Row&& row, Piece&& piece, Fin&& fin) {
+                                           int hn, int64_t n, int64_t nnz, int64_t n_tiles, int64_t tb,
+                                           int64_t te, const int32_t* __restrict__ ob, uint32_t* tk, double* head,
+                                           double* tail, Pre&& pre, Row&& row, Piece&& piece, Fin&& fin) {
     __shared__ AT prod[NW][TILE];
     const int lane = threadIdx.x & 63;
     AT* pw = prod[threadIdx.x >> 6];
-    const TileRange tr = wave_tiles<NW>(n_tiles);
+    const TileRange tr = wave_tiles<NW>(tb, te);
     const int64_t items = nnz + n;
     int64_t r_lo = 0, r_hi = 0;
     if (tr.first < tr.end) {

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "lz_ooc.h"
 #include "lz_spmv.h"
 
 namespace lz {
@@ -31,13 +32,20 @@ template <> struct Epi<true> { using T = float; };
 // kernel arguments, so the compiler knows them to be global memory and emits
 // global loads (pointers read from the state would give FLAT loads, which also
 // count against the LDS counter).
+// One launch covers tiles [tb, te).  A host-resident matrix takes one launch
+// per slab (slab = 0 .. nslab-1, all with the same grid): col_a/val_a then
+// point so that entry e of the matrix is col_a[e] for the slab's entries,
+// launch `slab` writes its alpha partials after those of the earlier slabs,
+// and the last launch reduces all of them.  A device-resident matrix is one
+// slab of all tiles.
 template <int P, int NW, bool XCACHE, bool F = false, bool OFF32 = false>
 __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                        typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
                                                        int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
                                                        uint32_t* tk, double* head, double* tail, double* part,
                                                        const int64_t* rp_a, const int32_t* col_a, const void* val_a,
-                                                       const int64_t* rp_b, const int32_t* col_b, const void* val_b) {
+                                                       const int64_t* rp_b, const int32_t* col_b, const void* val_b,
+                                                       int64_t tb, int64_t te, int slab, int nslab) {
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
@@ -52,6 +60,7 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
     if (st->mode == MODE_RESTART) {
         // Restart: a fresh random vector; the Gram-Schmidt kernels that follow
         // orthogonalise it against the basis.
+        if (slab != 0) return;
         const uint64_t rs = st->seed + ((uint64_t)st->restarts << 32);
         const int32_t* perm = st->perm;
         for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += (int64_t)gridDim.x * blockDim.x)
@@ -88,14 +97,15 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
         for (int i = threadIdx.x; i < hn; i += NW * 64) xs[i] = x[i];
         __syncthreads();
     }
-    spmv_tiles<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, pre, row,
-                                          piece, fin);
+    spmv_tiles<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, tb, te, ob, tk, head, tail,
+                                          pre, row, piece, fin);
     if (!need_alpha) return;
     apart = block_sum(apart, shd, NW);
-    if (threadIdx.x == 0) st_dev(&part[blockIdx.x], (double)apart);
+    if (threadIdx.x == 0) st_dev(&part[(int64_t)slab * gridDim.x + blockIdx.x], (double)apart);
+    if (slab != nslab - 1) return;
     __shared__ double shs[NW];
     if (last_block(&st->ticket[TK_SPMV], gridDim.x, &s_last)) {
-        const double alpha = (double)(E)ordered_sum_dev(part, gridDim.x, shs);
+        const double alpha = (double)(E)ordered_sum_dev(part, nslab * (int)gridDim.x, shs);
         if (threadIdx.x == 0) {
             st->alpha[j] = alpha;
             if (st->reorth == 0) {          // three-term recurrence only
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
     using WT = typename Tr<P>::W;
     if (st->status != 0) return;
     spmv_tiles<VT, AT, WAVES, false, false>(
-        rp, col, val, x, nullptr, 0, n, nnz, n_tiles, ob, tk, head, tail, [](int64_t) { return 0.0; },
+        rp, col, val, x, nullptr, 0, n, nnz, n_tiles, 0, n_tiles, ob, tk, head, tail, [](int64_t) { return 0.0; },
         [&](int64_t r, double acc, double) { y[r] = (WT)acc; }, [&](int64_t, double) {},
         [&](int64_t r, double acc) { y[r] = (WT)acc; });
 }
@@ -139,7 +149,7 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
             const int gx = (int)((g + 7) / 8 * 8);
             hipLaunchKernelGGL((k_spmv_step<P, XW, true, F>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
                                (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr,
-                               a.col, a.val, b.rp2, b.col2, b.val2);
+                               a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1);
             return;
         }
     }
@@ -147,15 +157,40 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
         if (off32)
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
+                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1);
         else
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, false>), dim3(p.g_tile), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2);
+                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1);
     }
 }
 
-void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
+// Host-resident matrix: one launch per slab, each on the slab's entries.
+template <int P, bool F = false>
+static hipError_t spmv_step_ooc(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
+    using VT = typename Tr<P>::V;
+    using WT = typename Tr<P>::W;
+    const bool off32 = (uint64_t)p.n * sizeof(VT) <= (uint64_t(1) << 32);
+    return ooc_pass(*p.ooc, b.st, s, [&](const int32_t* col, const void* val, int64_t tb, int64_t te, int k, int ns) {
+        if (off32)
+            hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(p.g_slab), dim3(BLOCK), 0, s, b.st,
+                               (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
+                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns);
+        else
+            hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, false>), dim3(p.g_slab), dim3(BLOCK), 0, s, b.st,
+                               (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
+                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns);
+    });
+}
+
+hipError_t launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s) {
+    if (p.ooc) {
+        switch (p.prec) {
+            case 0: return spmv_step_ooc<0>(p, b, a, s);
+            case 1: return p.fff ? spmv_step_ooc<1, true>(p, b, a, s) : spmv_step_ooc<1>(p, b, a, s);
+            default: return spmv_step_ooc<2>(p, b, a, s);
+        }
+    }
     switch (p.prec) {
         case 0: spmv_step_p<0>(p, b, a, s); break;
         case 1:
@@ -166,6 +201,7 @@ void launch_spmv_step(const Plan& p, const Bufs& b, const Csr& a, hipStream_t s)
             break;
         default: spmv_step_p<2>(p, b, a, s); break;
     }
+    return hipSuccess;
 }
 
 template <int P>

@@ -82,3 +82,69 @@ def test_workspace_size_grows_with_shape():
     c = lz.workspace_size(20000, 200000, 8, 24, "fp64")
     assert a > 10000 * 25 * 8 and b < a and c > a
     assert lz.workspace_size(0, 1, 1, 1, "fp64") == 0
+
+
+def _host_rowptr(n, nnz):
+    import numpy as np
+    rp = np.linspace(0, nnz, n + 1).astype(np.int64)
+    rp[-1] = nnz
+    return rp
+
+
+@pytest.mark.parametrize("case", ["K0", "m_gt_n", "slab_small", "resident_neg", "too_many_slabs", "rowptr0",
+                                  "hubs", "null_out"])
+def test_host_resident_arguments_rejected_before_gpu_work(case):
+    import numpy as np
+    L = lz.lib()
+    d = ctypes.c_void_p(16)
+    n, nnz, K, m, slab, res = 100, 1000, 2, 4, 4096, 0
+    rp = _host_rowptr(n, nnz)
+    opt = lz.Options()
+    L.lz_options_init(ctypes.byref(opt))
+    out = d
+    if case == "K0":
+        K = 0
+    elif case == "m_gt_n":
+        n, m = 3, 4
+        rp = _host_rowptr(n, nnz)
+    elif case == "slab_small":
+        slab = 2047
+    elif case == "resident_neg":
+        res = -1
+    elif case == "too_many_slabs":
+        rp = _host_rowptr(n, 1 << 26)          # 2^26 entries in slabs of 2048: more than 16384 slabs
+        slab = 2048
+    elif case == "rowptr0":
+        rp = rp.copy()
+        rp[0] = 1
+    elif case == "hubs":
+        opt.reorder = lz.REORDER["hubs"]
+    elif case == "null_out":
+        out = None
+    rc = L.lanczos_topk_host(rp.ctypes.data, d, d, n, K, m, 0, slab, res, None, out, d, ctypes.byref(opt), None)
+    assert rc == -1, case
+
+
+def test_host_resident_rejects_pageable_entries():
+    """Column indices and values in ordinary (pageable) host memory are
+    refused: the streamed copies need page-locked memory."""
+    import numpy as np
+    L = lz.lib()
+    n, nnz = 100, 1000
+    rp = _host_rowptr(n, nnz)
+    col = np.zeros(nnz, dtype=np.int32)
+    val = np.zeros(nnz, dtype=np.float64)
+    d = ctypes.c_void_p(16)
+    rc = L.lanczos_topk_host(rp.ctypes.data, col.ctypes.data, val.ctypes.data, n, 2, 4, 0, 0, 0, None, d, d,
+                             None, None)
+    assert rc == -1
+
+
+def test_host_workspace_excludes_the_relabelled_copy():
+    n, nnz = 100000, 2000000
+    for prec, vb in (("fp64", 8), ("fp32", 4), ("bf16", 2)):
+        dev = lz.workspace_size(n, nnz, 8, 24, prec)
+        host = lz.host_workspace_size(n, nnz, 8, 24, prec)
+        assert 0 < host < dev
+        assert dev - host >= nnz * (4 + vb) + 2 * n * 4 - 4 * 256
+    assert lz.host_workspace_size(0, 1, 1, 1, "fp64") == 0
