@@ -135,6 +135,114 @@ def run_mode(lz, dev_csr, K, m, mode, steps, warmup, ws):
                 vecs=out[1].T.cpu().numpy())
 
 
+# ------------------------------------------------------------ host-resident
+PCIE_PEAK_GBPS = 64.0      # PCIe 5.0 x16, one direction
+
+
+def host_main(args, W, lz, torch, eig_rel_err):
+    """The workload's head storage precision with the column indices and
+    values in pinned host memory (lanczos_topk_host), streamed in slabs at
+    every SpMV, for several shares of the entries kept on the device."""
+    import synth
+    rp, col, val, K, m = W["rp"], W["col"], W["val"], W["K"], W["m"]
+    n, nnz = rp.size - 1, int(rp[-1])
+    prec = mode_of(W["precisions"][0])[0]
+    vb = BYTES[prec][0]
+    dev = torch.device("cuda:0")
+    hrp = torch.from_numpy(np.ascontiguousarray(rp, np.int64))
+    hc = torch.from_numpy(np.ascontiguousarray(col, np.int32)).pin_memory()
+    st = synth.to_storage(val, prec)
+    hv = (torch.from_numpy(st.view(np.int16)).view(torch.bfloat16) if prec == "bf16"
+          else torch.from_numpy(np.ascontiguousarray(st))).pin_memory()
+    # What the host link delivers: pinned -> device copies of 256 MiB.
+    src = torch.empty(1 << 28, dtype=torch.uint8).pin_memory()
+    dst = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    link = 5 * (1 << 28) / (time.perf_counter() - t) / 1e9
+    del src, dst
+    print(f"[host] pinned->device copy {link:.1f} GB/s", file=sys.stderr, flush=True)
+    ws = torch.empty(lz.host_workspace_size(n, nnz, K, m, prec), dtype=torch.uint8, device=dev)
+    out = (torch.empty(K, dtype=torch.float64, device=dev), torch.empty(K, n, dtype=torch.float64, device=dev))
+    # The headline: every entry streamed, library slab size.  Then the
+    # resident sweep on slabs of nnz/8 entries (residency is by whole slabs).
+    sweep_slab = args.slab_nnz or max(2048, -(-nnz // 8))
+    cases = [(0.0, args.slab_nnz)] + [(float(x), sweep_slab) for x in args.resident.split(",")]
+    runs = []
+    for f, slab in cases:
+        res = nnz if f >= 1.0 else int(f * nnz)
+        kw = dict(slab_nnz=slab, resident_nnz=res, seed=0, workspace=ws, out=out, profile=True)
+        for _ in range(args.warmup):
+            lz.topk_host(hrp, hc, hv, K, m, prec, **kw)
+        torch.cuda.synchronize()
+        reps = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            reps.append(lz.topk_host(hrp, hc, hv, K, m, prec, **kw)[2])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        r = reps[-1]
+        passes = m + 1 + r["restarts"]
+        # Entries kept on the device: the streamed bytes are
+        # e_res (4+vb) + passes (nnz - e_res) (4+vb).
+        e_res = (passes * nnz * (4 + vb) - r["bytes_streamed"]) / ((passes - 1) * (4 + vb))
+        t_spmv = float(np.mean([x["t_spmv_ms"] for x in reps]))
+        per_pass = (nnz - e_res) * (4 + vb)
+        runs.append(dict(resident_frac=f, slab_nnz=slab or (1 << 24), resident_entries=int(round(e_res)),
+                         solves_per_s=args.steps / el,
+                         ms_per_solve=el / args.steps * 1e3, spmv_ms=t_spmv,
+                         h2d_bytes_per_spmv=int(round(per_pass)),
+                         h2d_gbps=per_pass / (t_spmv * 1e-3) / 1e9 if per_pass > 0 else None,
+                         bytes_streamed_per_solve=r["bytes_streamed"],
+                         finish_ms=float(np.mean([x["t_finish_ms"] for x in reps])),
+                         vals=out[0].cpu().numpy()))
+        x = runs[-1]
+        gb = f"{x['h2d_gbps']:.1f} GB/s" if x["h2d_gbps"] else "no streaming"
+        print(f"[host] slab {x['slab_nnz']} resident {f:.2f}: {x['solves_per_s']:.2f} solves/s, "
+              f"spmv {t_spmv:.3f} ms ({gb})", file=sys.stderr, flush=True)
+    head = runs[0]
+    line = {
+        "metric": METRIC,
+        "value": head["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}-host", "description": W["desc"] + "; column indices and values "
+                   "in pinned host memory, streamed to the device at every SpMV", "n": n, "nnz": nnz, "K": K,
+                   "m": m, "precision": prec, "reorth": "twice", "slab_nnz": head["slab_nnz"],
+                   "resident_frac": 0.0, "parallelism": "single-gpu"},
+        "roofline": {"bound": "pcie", "kernel": "host-to-device slab copies of the Lanczos-step SpMV",
+                     "achieved": head["h2d_gbps"], "peak": PCIE_PEAK_GBPS, "unit": "GB/s",
+                     "frac": head["h2d_gbps"] / PCIE_PEAK_GBPS if head["h2d_gbps"] else None,
+                     "traffic": None, "bytes_per_launch": head["h2d_bytes_per_spmv"]},
+        "link_copy_gbps": link,
+        "resident_sweep": [{k: v for k, v in x.items() if k != "vals"} for x in runs[1:]],
+        # Every slab size and resident share gives the same solve, bit for bit.
+        "identical_across_runs": all(np.array_equal(x["vals"], head["vals"]) for x in runs[1:]),
+    }
+    if not args.no_cpu and nnz <= 64_000_000:
+        import oracle
+        t = time.perf_counter()
+        ref = oracle.topk(rp, col, val, K, m, seed=0, report=False)
+        dt = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "sample": f"one whole FP64 oracle solve of the same workload ({dt:.1f} s)"}
+        line["eig_rel_err"] = eig_rel_err(head["vals"], ref["vals"])
+    print(json.dumps(line), flush=True)
+
+
 # ------------------------------------------------------------------ serving
 def serving_pool(n_pool: int, seed: int = 0):
     """Distinct matrices of the request stream: n log-uniform in [1e4, 2e6],
@@ -381,6 +489,12 @@ def main():
                     help="first run a plain copy kernel (1 GiB read + 1 GiB written, three launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic of the other kernels")
     ap.add_argument("--precisions", default=None, help="comma list overriding the workload's precisions")
+    ap.add_argument("--host", action="store_true",
+                    help="matrix entries in pinned host memory, streamed at every SpMV (lanczos_topk_host)")
+    ap.add_argument("--resident", default="0,0.25,0.5,0.75,1",
+                    help="host: comma list of the shares of entries kept on the device (slabs of nnz/8)")
+    ap.add_argument("--slab-nnz", type=int, default=0,
+                    help="host: entries per streamed slab for every run (0: library default, nnz/8 for the sweep)")
     ap.add_argument("--study", default=None, choices=["reorth", "precision"],
                     help="reorth: accuracy and time of the reorthogonalisation modes (none/once/twice/"
                          "selective) for K in {8, 16, 32}, m = 3K, on the workload; precision: all-double, "
@@ -420,6 +534,8 @@ def main():
         return study_reorth(args, W, lz, torch, device_csr, eig_rel_err)
     if args.study == "precision":
         return study_precision(args, lz, torch, device_csr, eig_rel_err)
+    if args.host:
+        return host_main(args, W, lz, torch, eig_rel_err)
     ws_bytes = max(lz.workspace_size(n, nnz, K, m, mode_of(p)[0]) for p in W["precisions"])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 

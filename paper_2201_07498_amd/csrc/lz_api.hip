@@ -133,6 +133,7 @@ namespace lz {
 // matrix entries stay in host memory and a.rowptr is a host array.
 int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_vals, double* out_vecs,
               lz_report* report, HostCsr* hc) {
+    const hipStream_t user = s;
     const int64_t n = a.n;
     const int32_t K = p.K, m = p.m;
     int rc = LZ_OK;
@@ -178,6 +179,11 @@ int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_val
             LZ_HIP(hipEventRecord(pev[0], s));
         }
         if (hc) {
+            const hipError_t be = ooc_begin(hc->ooc, &s);
+            if (be != hipSuccess) {
+                rc = LZ_ERR_HIP;
+                goto done;
+            }
             // Row pointers to the device (the slot of the relabelled ones).
             LZ_HIP(hipMemcpyAsync(b.rp2, a.rowptr, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
             a.rowptr = b.rp2;
@@ -265,7 +271,10 @@ int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_val
     }
 done:
     if (owned || hc) (void)hipStreamSynchronize(s);
-    if (hc) ooc_release(hc->ooc);
+    if (hc) {
+        if (hc->ooc.ks && ooc_end(hc->ooc, user) != hipSuccess && rc == LZ_OK) rc = LZ_ERR_HIP;
+        ooc_release(hc->ooc);
+    }
     if (owned) (void)hipFree(ws);
     for (hipEvent_t e : iev) (void)hipEventDestroy(e);
     for (hipEvent_t e : pev)

@@ -40,7 +40,9 @@ struct Ooc {
     char* rval = nullptr;
     int32_t* scol[2] = {nullptr, nullptr};   // staging buffers of the streamed slabs
     char* sval[2] = {nullptr, nullptr};
+    hipStream_t ks = nullptr;        // compute stream of the solve (default priority)
     hipStream_t cs = nullptr;        // copy stream (default priority)
+    hipEvent_t join = nullptr;       // orders the compute stream after the caller's stream and back
     hipEvent_t ready[2] = {nullptr, nullptr};   // staging buffer i holds its slab
     hipEvent_t freed[2] = {nullptr, nullptr};   // the kernel reading staging buffer i is done
     int next = 0;                    // staging buffer of the next streamed slab
@@ -111,10 +113,18 @@ struct HostCsr {
 int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_vals, double* out_vecs,
               lz_report* report, HostCsr* hc);
 
+// The solve runs on a compute stream of its own (cached per host thread and
+// device with the copy stream and the events), ordered after the caller's
+// stream, so that the copy and compute streams are both created streams
+// whatever stream the caller passes.  *s becomes that stream.
+hipError_t ooc_begin(Ooc& o, hipStream_t* s);
+// Makes the caller's stream wait for the compute stream.
+hipError_t ooc_end(Ooc& o, hipStream_t user);
+
 // Plans the slabs from the device tile table and sets up the buffers and the
 // copy stream; copies the resident slabs.  slab_nnz >= TILE.
 hipError_t ooc_prepare(Plan& p, const Bufs& b, Ooc& o, int64_t slab_nnz, int64_t resident_nnz, hipStream_t s);
-// Waits for the copy stream and frees what ooc_prepare allocated.
+// Waits for both streams and frees what ooc_begin and ooc_prepare allocated.
 void ooc_release(Ooc& o);
 
 }  // namespace lz

@@ -8,6 +8,73 @@
 
 namespace lz {
 
+namespace {
+// Streams and events of the host-resident solves, created on first use per
+// host thread and device and kept for the process: a freshly created pair of
+// streams has been measured to block the host thread for milliseconds during
+// its first few dozen copies and cross-stream waits.
+struct StreamSet {
+    hipStream_t ks = nullptr, cs = nullptr;
+    hipEvent_t join = nullptr;
+    hipEvent_t ready[2] = {nullptr, nullptr};
+    hipEvent_t freed[2] = {nullptr, nullptr};
+};
+constexpr int MAX_DEVICES = 64;
+thread_local StreamSet stream_sets[MAX_DEVICES];
+
+hipError_t stream_set(StreamSet** out) {
+    int d = 0;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    if (d < 0 || d >= MAX_DEVICES) return hipErrorInvalidDevice;
+    StreamSet& S = stream_sets[d];
+    if (!S.join) {
+        StreamSet N;
+        const unsigned ef = hipEventDisableTiming;
+        if ((e = hipStreamCreateWithFlags(&N.ks, hipStreamNonBlocking)) == hipSuccess &&
+            (e = hipStreamCreateWithFlags(&N.cs, hipStreamNonBlocking)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&N.ready[0], ef)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&N.ready[1], ef)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&N.freed[0], ef)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&N.freed[1], ef)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&N.join, ef)) == hipSuccess) {
+            S = N;
+        } else {
+            for (hipStream_t x : {N.ks, N.cs})
+                if (x) (void)hipStreamDestroy(x);
+            for (hipEvent_t x : {N.ready[0], N.ready[1], N.freed[0], N.freed[1], N.join})
+                if (x) (void)hipEventDestroy(x);
+            return e;
+        }
+    }
+    *out = &S;
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t ooc_begin(Ooc& o, hipStream_t* s) {
+    StreamSet* S = nullptr;
+    hipError_t e = stream_set(&S);
+    if (e != hipSuccess) return e;
+    o.ks = S->ks;
+    o.cs = S->cs;
+    o.join = S->join;
+    for (int i = 0; i < 2; ++i) {
+        o.ready[i] = S->ready[i];
+        o.freed[i] = S->freed[i];
+    }
+    if ((e = hipEventRecord(o.join, *s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(o.ks, o.join, 0)) != hipSuccess) return e;
+    *s = o.ks;
+    return hipSuccess;
+}
+
+hipError_t ooc_end(Ooc& o, hipStream_t user) {
+    hipError_t e;
+    if ((e = hipEventRecord(o.join, o.ks)) != hipSuccess) return e;
+    return hipStreamWaitEvent(user, o.join, 0);
+}
+
 hipError_t ooc_prepare(Plan& p, const Bufs& b, Ooc& o, int64_t slab_nnz, int64_t resident_nnz, hipStream_t s) {
     hipError_t e;
     // Status of the row-pointer checks and the tile table built from them.
@@ -75,28 +142,22 @@ hipError_t ooc_prepare(Plan& p, const Bufs& b, Ooc& o, int64_t slab_nnz, int64_t
             if ((e = hipMalloc((void**)&o.scol[i], me * 4)) != hipSuccess) return e;
             if ((e = hipMalloc((void**)&o.sval[i], me * o.vb)) != hipSuccess) return e;
         }
-        if ((e = hipStreamCreateWithFlags(&o.cs, hipStreamNonBlocking)) != hipSuccess) return e;
-        for (int i = 0; i < 2; ++i) {
-            if ((e = hipEventCreateWithFlags(&o.ready[i], hipEventDisableTiming)) != hipSuccess) return e;
-            if ((e = hipEventCreateWithFlags(&o.freed[i], hipEventDisableTiming)) != hipSuccess) return e;
+        for (int i = 0; i < 2; ++i)
             if ((e = hipEventRecord(o.freed[i], s)) != hipSuccess) return e;
-        }
     }
     return hipSuccess;
 }
 
 void ooc_release(Ooc& o) {
-    if (o.cs) {
-        (void)hipStreamSynchronize(o.cs);
-        (void)hipStreamDestroy(o.cs);
-        o.cs = nullptr;
-    }
+    // The streams and events stay cached for the next solve on this thread.
+    if (o.ks) (void)hipStreamSynchronize(o.ks);
+    if (o.cs) (void)hipStreamSynchronize(o.cs);
+    o.ks = o.cs = nullptr;
+    o.join = nullptr;
     for (int i = 0; i < 2; ++i) {
-        if (o.ready[i]) (void)hipEventDestroy(o.ready[i]);
-        if (o.freed[i]) (void)hipEventDestroy(o.freed[i]);
+        o.ready[i] = o.freed[i] = nullptr;
         if (o.scol[i]) (void)hipFree(o.scol[i]);
         if (o.sval[i]) (void)hipFree(o.sval[i]);
-        o.ready[i] = o.freed[i] = nullptr;
         o.scol[i] = nullptr;
         o.sval[i] = nullptr;
     }
