@@ -172,7 +172,7 @@ def host_main(args, W, lz, torch, eig_rel_err):
     # The headline: every entry streamed, library slab size.  Then the
     # resident sweep on slabs of nnz/8 entries (residency is by whole slabs).
     sweep_slab = args.slab_nnz or max(2048, -(-nnz // 8))
-    cases = [(0.0, args.slab_nnz)] + [(float(x), sweep_slab) for x in args.resident.split(",")]
+    cases = [(0.0, args.slab_nnz)] + [(float(x), sweep_slab) for x in args.resident.split(",") if x]
     runs = []
     for f, slab in cases:
         res = nnz if f >= 1.0 else int(f * nnz)
