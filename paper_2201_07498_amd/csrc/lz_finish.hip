@@ -411,6 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
     __shared__ VT sval_all[WAVES][TILE];
     if (st->status != 0) return;
     const bool rl = st->reordered != 0;
+    const bool pk = rl && st->packed != 0;
     const int64_t* rp = rl ? rp_b : rp_a;
     const int32_t* col = rl ? col_b : col_a;
     const VT* val = (const VT*)(rl ? val_b : val_a);
@@ -434,9 +435,12 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
         const int64_t r_lo = ob[t], r_hi = ob[t + 1];
         const int64_t t0 = t * TILE - r_lo;
         const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
+        // A column-sorted tile goes back to row order in LDS.
         for (int i = lane; i < cnt; i += 64) {
-            scol[i] = col[t0 + i];
-            sval[i] = val[t0 + i];
+            const uint32_t cw = (uint32_t)col[t0 + i];
+            const int sl = pk ? (int)(cw & PACK_SLOTMASK) : i;
+            scol[sl] = pk ? (int)(cw >> PACK_SLOTBITS) : (int)cw;
+            sval[sl] = val[t0 + i];
         }
         wave_sync();
         const bool split_head = r_lo < r_hi && rp[r_lo] < t0;

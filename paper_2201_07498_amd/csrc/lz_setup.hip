@@ -113,6 +113,7 @@ __global__ void k_reorder_decide(State* st, const int64_t* rp, const int32_t* co
             use = n >= REORDER_MIN_N && (double)st->maxdeg * (double)n >= REORDER_SKEW * (double)nnz;
     }
     st->reordered = use ? 1 : 0;
+    st->packed = use && n < (int64_t(1) << PACK_COLBITS) ? 1 : 0;
     st->crp = use ? rp2 : rp;
     st->ccol = use ? col2 : col;
     st->cval = use ? val2 : val;
@@ -286,7 +287,9 @@ __global__ __launch_bounds__(BLOCK) void k_rl_rowlen(const State* st, const int6
 // shift from new to old position (rp[perm[row]] - rp2[row]).  Each lane then
 // takes its 16 entries together: a fixed-step search over the staged rows,
 // then all 16 col/val loads, then all 16 iperm gathers, so a tile costs two
-// rounds of requests.
+// rounds of requests.  For n < 2^22 the tile is then sorted by column in
+// LDS and stored packed (col << 10 | position in row order): the SpMV's
+// gathers of one wavefront instruction then hit neighbouring columns.
 constexpr int FILL_WAVES = 2;
 template <class VT>
 __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, const int64_t* __restrict__ rp,
@@ -300,6 +303,7 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
     __shared__ int64_t srp[FILL_WAVES][TILE + 2];
     __shared__ int64_t sdel[FILL_WAVES][TILE + 1];
     if (!st->reordered) return;
+    const bool packed = st->packed != 0;
     const int lane = threadIdx.x & 63;
     int64_t* s = srp[threadIdx.x >> 6];
     int64_t* d = sdel[threadIdx.x >> 6];
@@ -335,13 +339,51 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
         }
 #pragma unroll
         for (int e = 0; e < TP; ++e) c[e] = iperm[c[e]];
+        if (!packed) {
+#pragma unroll
+            for (int e = 0; e < TP; ++e) {
+                const int k = e * 64 + lane;
+                if (k < cnt) {
+                    col2[t0 + k] = c[e];
+                    val2[t0 + k] = v[e];
+                }
+            }
+            wave_sync();
+            continue;
+        }
+        // Column-sorted tile: keys (col << 10 | position) in the LDS of the
+        // row search (no longer read), values by position, a bitonic sort of
+        // the 1024 keys (unique, so the order is fixed; padding sorts last),
+        // then the sorted keys and their values.
+        wave_sync();
+        uint32_t* key = reinterpret_cast<uint32_t*>(s);
+        VT* sv = reinterpret_cast<VT*>(d);
 #pragma unroll
         for (int e = 0; e < TP; ++e) {
             const int k = e * 64 + lane;
-            if (k < cnt) {
-                col2[t0 + k] = c[e];
-                val2[t0 + k] = v[e];
+            key[k] = k < cnt ? ((uint32_t)c[e] << PACK_SLOTBITS) | (uint32_t)k : 0xffffffffu;
+            sv[k] = v[e];
+        }
+        wave_sync();
+        for (int kk = 2; kk <= TILE; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                for (int i = lane; i < TILE / 2; i += 64) {
+                    const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                    const int b2 = a + j;
+                    const uint32_t x = key[a], y = key[b2];
+                    if ((x > y) == ((a & kk) == 0)) {
+                        key[a] = y;
+                        key[b2] = x;
+                    }
+                }
+                wave_sync();
             }
+        }
+        for (int k = lane; k < cnt; k += 64) {
+            const uint32_t kv = key[k];
+            col2[t0 + k] = (int32_t)kv;
+            val2[t0 + k] = sv[kv & PACK_SLOTMASK];
         }
         wave_sync();
     }

@@ -141,8 +141,9 @@ template <class VT, class AT, int NW, bool CACHED, bool OFF32, class Pre, class 
 __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const VT* __restrict__ x, const VT* xs,
                                            int hn, int64_t n, int64_t nnz, int64_t n_tiles, int64_t tb,
-                                           int64_t te, const int32_t* __restrict__ ob, uint32_t* tk, double* head,
-                                           double* tail, Pre&& pre, Row&& row, Piece&& piece, Fin&& fin) {
+                                           int64_t te, bool packed, const int32_t* __restrict__ ob, uint32_t* tk,
+                                           double* head, double* tail, Pre&& pre, Row&& row, Piece&& piece,
+                                           Fin&& fin) {
     __shared__ AT prod[NW][TILE];
     const int lane = threadIdx.x & 63;
     AT* pw = prod[threadIdx.x >> 6];
@@ -176,7 +177,8 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
         const int64_t rb_hi = r_hi < n ? rp[r_hi] : 0;
         // Entries of the tile, then the gathers of x.  Lanes past the end
         // re-read the tile's last entry (same cache line), so every load is
-        // unconditional; their products land beyond cnt and are never read.
+        // unconditional; their products land beyond cnt and are never read
+        // (or, in a column-sorted tile, rewrite the last entry's product).
         if (cnt > 0) {
             int ci[TP];
             VT vv[TP];
@@ -197,6 +199,15 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
                     vv[q] = val[p];
                 }
             }
+            // Column-sorted tiles: the product goes to the entry's position
+            // in row order, so the row sums below add the same values in the
+            // same order as for a tile stored in row order.
+            int sl[TP];
+#pragma unroll
+            for (int q = 0; q < TP; ++q) {
+                sl[q] = packed ? (int)((uint32_t)ci[q] & PACK_SLOTMASK) : q * 64 + lane;
+                ci[q] = packed ? (int)((uint32_t)ci[q] >> PACK_SLOTBITS) : ci[q];
+            }
 #pragma unroll
             for (int q = 0; q < TP; ++q) {
                 VT xv;
@@ -206,7 +217,7 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
                     xv = *(const VT*)((const char*)x + (uint32_t)ci[q] * (uint32_t)sizeof(VT));
                 else
                     xv = x[ci[q]];
-                pw[q * 64 + lane] = to_a(vv[q], AT(0)) * to_a(xv, AT(0));
+                pw[sl[q]] = to_a(vv[q], AT(0)) * to_a(xv, AT(0));
             }
         }
         wave_sync();
