@@ -291,6 +291,38 @@ __global__ __launch_bounds__(BLOCK) void k_rl_rowlen(const State* st, const int6
 // LDS and stored packed (col << 10 | position in row order): the SpMV's
 // gathers of one wavefront instruction then hit neighbouring columns.
 constexpr int FILL_WAVES = 2;
+
+// Bitonic sort of the 1024 keys of one wavefront, ascending; element
+// lane*16 + r is kr[r] of that lane.  Exchanges between elements 16 or more
+// apart are lane shuffles, the others stay in the lane's registers.
+__device__ __forceinline__ void sort_tile_keys(uint32_t (&kr)[TP], int lane) {
+#pragma unroll
+    for (int kk = 2; kk <= TILE; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= TP) {
+#pragma unroll
+                for (int r = 0; r < TP; ++r) {
+                    const int i = lane * TP + r;
+                    const uint32_t o = (uint32_t)__shfl_xor((int)kr[r], j / TP, 64);
+                    const uint32_t lo = min(kr[r], o), hi = max(kr[r], o);
+                    kr[r] = (((i & j) == 0) == ((i & kk) == 0)) ? lo : hi;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < TP; ++r) {
+                    if ((r & j) != 0) continue;
+                    const int r2 = r | j;
+                    const bool asc = ((lane * TP + r) & kk) == 0;
+                    const uint32_t a = kr[r], b = kr[r2];
+                    const bool sw = (a > b) == asc;
+                    kr[r] = sw ? b : a;
+                    kr[r2] = sw ? a : b;
+                }
+            }
+        }
+    }
+}
 template <class VT>
 __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, const int64_t* __restrict__ rp,
                                                             const int32_t* __restrict__ col,
@@ -351,10 +383,11 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
             wave_sync();
             continue;
         }
-        // Column-sorted tile: keys (col << 10 | position) in the LDS of the
-        // row search (no longer read), values by position, a bitonic sort of
-        // the 1024 keys (unique, so the order is fixed; padding sorts last),
-        // then the sorted keys and their values.
+        // Column-sorted tile: keys (col << 10 | position) go through the LDS
+        // of the row search (no longer read) so that each lane holds 16
+        // consecutive ones, the wavefront sorts them in registers (unique
+        // keys, so the order is fixed; padding sorts last), and the sorted
+        // keys come back through LDS for coalesced stores with their values.
         wave_sync();
         uint32_t* key = reinterpret_cast<uint32_t*>(s);
         VT* sv = reinterpret_cast<VT*>(d);
@@ -365,25 +398,22 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
             sv[k] = v[e];
         }
         wave_sync();
-        for (int kk = 2; kk <= TILE; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
+        uint32_t kr[TP];
 #pragma unroll
-                for (int i = lane; i < TILE / 2; i += 64) {
-                    const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-                    const int b2 = a + j;
-                    const uint32_t x = key[a], y = key[b2];
-                    if ((x > y) == ((a & kk) == 0)) {
-                        key[a] = y;
-                        key[b2] = x;
-                    }
-                }
-                wave_sync();
+        for (int r = 0; r < TP; ++r) kr[r] = key[lane * TP + r];
+        sort_tile_keys(kr, lane);
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < TP; ++r) key[lane * TP + r] = kr[r];
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < TP; ++e) {
+            const int k = e * 64 + lane;
+            if (k < cnt) {
+                const uint32_t kv = key[k];
+                col2[t0 + k] = (int32_t)kv;
+                val2[t0 + k] = sv[kv & PACK_SLOTMASK];
             }
-        }
-        for (int k = lane; k < cnt; k += 64) {
-            const uint32_t kv = key[k];
-            col2[t0 + k] = (int32_t)kv;
-            val2[t0 + k] = sv[kv & PACK_SLOTMASK];
         }
         wave_sync();
     }
