@@ -411,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
     __shared__ VT sval_all[WAVES][TILE];
     if (st->status != 0) return;
     const bool rl = st->reordered != 0;
-    const bool pk = rl && st->packed != 0;
+    const int packing = rl ? st->packed : PACK_NONE;
     const int64_t* rp = rl ? rp_b : rp_a;
     const int32_t* col = rl ? col_b : col_a;
     const VT* val = (const VT*)(rl ? val_b : val_a);
@@ -430,19 +430,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
         z = group_sum(z, KB2);
         return act ? z + ld_dev(&head[t2 * KB2 + k]) : 0.0;
     };
-    const TileRange tr = wave_tiles(tb, te);
-    for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
+    // Rows of tile t from its entries in row order, scol/sval[0..cnt).
+    auto tile_body = [&](int64_t t, const int* scol, const VT* sval) {
         const int64_t r_lo = ob[t], r_hi = ob[t + 1];
         const int64_t t0 = t * TILE - r_lo;
         const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
-        // A column-sorted tile goes back to row order in LDS.
-        for (int i = lane; i < cnt; i += 64) {
-            const uint32_t cw = (uint32_t)col[t0 + i];
-            const int sl = pk ? (int)(cw & PACK_SLOTMASK) : i;
-            scol[sl] = pk ? (int)(cw >> PACK_SLOTBITS) : (int)cw;
-            sval[sl] = val[t0 + i];
-        }
-        wave_sync();
         const bool split_head = r_lo < r_hi && rp[r_lo] < t0;
         double head_z = 0.0;
         for (int64_t base = r_lo; base < r_hi; base += G) {
@@ -492,6 +484,51 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(State* st, const double* __restr
                 }
             }
         }
+    };
+    if (packing == PACK_GROUP) {
+        // Group-sorted storage: the workgroup puts a group's entries back in
+        // row order in its LDS, then each wavefront takes its tile.
+        static_assert(WAVES == GROUP_TILES, "one wavefront per tile of a group");
+        int* gcol = &scol_all[0][0];
+        VT* gval = &sval_all[0][0];
+        const int w = threadIdx.x >> 6;
+        const int64_t n_groups = (n_tiles + GROUP_TILES - 1) / GROUP_TILES;
+        const int64_t xcd = blockIdx.x & 7, nb8 = gridDim.x >> 3;
+        const int64_t lo = n_groups * xcd / 8, hi = n_groups * (xcd + 1) / 8;
+        for (int64_t gi = lo + (blockIdx.x >> 3); gi < hi; gi += nb8) {
+            const int64_t tg = gi * GROUP_TILES, tend = min<int64_t>(tg + GROUP_TILES, n_tiles);
+            const int64_t g0 = tg * TILE - ob[tg];
+            const int64_t gend = tend >= n_tiles ? nnz : tend * TILE - ob[tend];
+            for (int64_t i = threadIdx.x; i < gend - g0; i += BLOCK) {
+                const uint32_t cw = (uint32_t)col[g0 + i];
+                const int sl = (int)(cw & GROUP_SLOTMASK);
+                gcol[sl] = (int)(cw >> GROUP_SLOTBITS);
+                gval[sl] = val[g0 + i];
+            }
+            __syncthreads();
+            const int64_t t = tg + w;
+            if (t < n_tiles) {
+                const int off = (int)(t * TILE - ob[t] - g0);
+                tile_body(t, gcol + off, gval + off);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    const TileRange tr = wave_tiles(tb, te);
+    for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
+        const int64_t r_lo = ob[t], r_hi = ob[t + 1];
+        const int64_t t0 = t * TILE - r_lo;
+        const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
+        // A tile-sorted tile goes back to row order in LDS.
+        for (int i = lane; i < cnt; i += 64) {
+            const uint32_t cw = (uint32_t)col[t0 + i];
+            const int sl = packing == PACK_TILE ? (int)(cw & PACK_SLOTMASK) : i;
+            scol[sl] = packing == PACK_TILE ? (int)(cw >> PACK_SLOTBITS) : (int)cw;
+            sval[sl] = val[t0 + i];
+        }
+        wave_sync();
+        tile_body(t, scol, sval);
         wave_sync();
     }
 }

@@ -20,12 +20,19 @@ constexpr int OBLOCK = 1024;   // orthogonalisation workgroup (16 wave64)
 constexpr int DGRID = 1024;    // grid cap of the other dense kernels (workgroups of BLOCK threads)
 constexpr int SGRID = 2048;    // SpMV grid cap (workgroups)
 constexpr int GRAM_PARTS = 1024; // Gram kernel grid cap (per-workgroup 64x64 partials)
-// Column-sorted tiles of the relabelled matrix (n < 2^PACK_COLBITS): each
-// tile's entries are stored in column order and each column word holds
-// (col << PACK_SLOTBITS) | (the entry's position in the tile's row order).
+// Column-sorted storage of the relabelled matrix.  State.packed = PACK_TILE
+// (n < 2^22): each tile's entries are stored in column order and each column
+// word holds (col << PACK_SLOTBITS) | (the entry's position in the tile's row
+// order).  PACK_GROUP (n <= 2^20): the same over groups of GROUP_TILES
+// consecutive tiles, with GROUP_SLOTBITS-bit positions in the group.
+enum Packing { PACK_NONE = 0, PACK_TILE = 1, PACK_GROUP = 2 };
 constexpr int PACK_SLOTBITS = 10;   // TILE = 2^10 positions
 constexpr int PACK_COLBITS = 22;
 constexpr uint32_t PACK_SLOTMASK = (1u << PACK_SLOTBITS) - 1u;
+constexpr int GROUP_TILES = 4;
+constexpr int GROUP_SLOTBITS = 12;  // GROUP_TILES * TILE = 2^12 positions
+constexpr int GROUP_COLBITS = 20;
+constexpr uint32_t GROUP_SLOTMASK = (1u << GROUP_SLOTBITS) - 1u;
 
 enum Mode { MODE_NORMAL = 0, MODE_RESTART = 1 };
 
@@ -57,7 +64,7 @@ struct State {
     const int32_t* perm;       // relabelled row -> original row (null: identity)
     const int32_t* iperm;      // original row -> relabelled row
     int32_t reorder, reordered;
-    int32_t packed, pad2;      // relabelled tiles sorted by column, col words packed (PACK_* below)
+    int32_t packed, pad2;      // Packing of the relabelled copy
     unsigned long long maxdeg; // longest row of the input
     double alpha[MMAX + 8];
     double beta[MMAX + 8];     // beta[k] couples columns k-1 and k; beta[0] = 0

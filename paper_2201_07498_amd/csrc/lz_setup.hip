@@ -113,7 +113,9 @@ __global__ void k_reorder_decide(State* st, const int64_t* rp, const int32_t* co
             use = n >= REORDER_MIN_N && (double)st->maxdeg * (double)n >= REORDER_SKEW * (double)nnz;
     }
     st->reordered = use ? 1 : 0;
-    st->packed = use && n < (int64_t(1) << PACK_COLBITS) ? 1 : 0;
+    st->packed = !use ? PACK_NONE
+                 : n <= (int64_t(1) << GROUP_COLBITS) ? PACK_GROUP
+                 : n < (int64_t(1) << PACK_COLBITS) ? PACK_TILE : PACK_NONE;
     st->crp = use ? rp2 : rp;
     st->ccol = use ? col2 : col;
     st->cval = use ? val2 : val;
@@ -292,18 +294,34 @@ __global__ __launch_bounds__(BLOCK) void k_rl_rowlen(const State* st, const int6
 // gathers of one wavefront instruction then hit neighbouring columns.
 constexpr int FILL_WAVES = 2;
 
-// Bitonic sort of the 1024 keys of one wavefront, ascending; element
-// lane*16 + r is kr[r] of that lane.  Exchanges between elements 16 or more
-// apart are lane shuffles, the others stay in the lane's registers.
-__device__ __forceinline__ void sort_tile_keys(uint32_t (&kr)[TP], int lane) {
+// Bitonic sort, ascending, of the N keys of the threads 0 .. N/16-1 of a
+// workgroup: element tid*16 + r is kr[r] of thread tid.  Exchanges between
+// elements less than 16 apart stay in a thread's registers, those within a
+// wavefront are lane shuffles, and those between wavefronts (N > 1024) go
+// through xbuf (N keys of LDS) between barriers, so every thread of the
+// workgroup must call it.
+template <int N>
+__device__ __forceinline__ void sort_keys(uint32_t (&kr)[TP], int tid, uint32_t* xbuf) {
 #pragma unroll
-    for (int kk = 2; kk <= TILE; kk <<= 1) {
+    for (int kk = 2; kk <= N; kk <<= 1) {
 #pragma unroll
         for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= TP) {
+            if (j >= 64 * TP) {
+#pragma unroll
+                for (int r = 0; r < TP; ++r) xbuf[tid * TP + r] = kr[r];
+                __syncthreads();
 #pragma unroll
                 for (int r = 0; r < TP; ++r) {
-                    const int i = lane * TP + r;
+                    const int i = tid * TP + r;
+                    const uint32_t o = xbuf[i ^ j];
+                    const uint32_t lo = min(kr[r], o), hi = max(kr[r], o);
+                    kr[r] = (((i & j) == 0) == ((i & kk) == 0)) ? lo : hi;
+                }
+                __syncthreads();
+            } else if (j >= TP) {
+#pragma unroll
+                for (int r = 0; r < TP; ++r) {
+                    const int i = tid * TP + r;
                     const uint32_t o = (uint32_t)__shfl_xor((int)kr[r], j / TP, 64);
                     const uint32_t lo = min(kr[r], o), hi = max(kr[r], o);
                     kr[r] = (((i & j) == 0) == ((i & kk) == 0)) ? lo : hi;
@@ -313,7 +331,7 @@ __device__ __forceinline__ void sort_tile_keys(uint32_t (&kr)[TP], int lane) {
                 for (int r = 0; r < TP; ++r) {
                     if ((r & j) != 0) continue;
                     const int r2 = r | j;
-                    const bool asc = ((lane * TP + r) & kk) == 0;
+                    const bool asc = ((tid * TP + r) & kk) == 0;
                     const uint32_t a = kr[r], b = kr[r2];
                     const bool sw = (a > b) == asc;
                     kr[r] = sw ? b : a;
@@ -323,6 +341,51 @@ __device__ __forceinline__ void sort_tile_keys(uint32_t (&kr)[TP], int lane) {
         }
     }
 }
+
+// One wavefront's share of the fill: the 16 entries of each lane of tile t
+// (entry t0 + e*64 + lane, clamped to the tile) with columns relabelled.  The
+// tile's rows are staged in s/d first: their first new position and the shift
+// from new to old position (rp[perm[row]] - rp2[row]).  Returns the tile's
+// entry count (0: row ends only, nothing loaded).
+template <class VT>
+__device__ __forceinline__ int fill_tile_gather(int64_t t, const int64_t* __restrict__ rp,
+                                                const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                                int64_t n, int64_t nnz, const int32_t* __restrict__ ob,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
+                                                const int64_t* __restrict__ rp2, int64_t* s, int64_t* d, int lane,
+                                                int64_t* t0_out, int32_t (&c)[TP], VT (&v)[TP]) {
+    const int64_t r_lo = ob[t], r_hi = ob[t + 1];
+    const int64_t t0 = t * TILE - r_lo;
+    *t0_out = t0;
+    const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
+    if (cnt <= 0) return 0;
+    // Rows r_lo .. r_last touch the tile (at most TILE + 1 of them).
+    const int64_t r_last = min(r_hi, n - 1);
+    const int nr = (int)(r_last - r_lo + 1);
+    for (int i = lane; i <= nr; i += 64) s[i] = rp2[r_lo + i];
+    for (int i = lane; i < nr; i += 64) d[i] = rp[perm[r_lo + i]] - rp2[r_lo + i];
+    wave_sync();
+    int64_t src[TP];
+#pragma unroll
+    for (int e = 0; e < TP; ++e) {
+        const int64_t q = t0 + min(e * 64 + lane, cnt - 1);
+        // Largest i < nr with s[i] <= q (the row whose range holds q).
+        int lo = 0;
+#pragma unroll
+        for (int step = TILE; step > 0; step >>= 1)
+            if (lo + step < nr && s[lo + step] <= q) lo += step;
+        src[e] = q + d[lo];
+    }
+#pragma unroll
+    for (int e = 0; e < TP; ++e) {
+        c[e] = col[src[e]];
+        v[e] = val[src[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < TP; ++e) c[e] = iperm[c[e]];
+    return cnt;
+}
+
 template <class VT>
 __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, const int64_t* __restrict__ rp,
                                                             const int32_t* __restrict__ col,
@@ -335,42 +398,18 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
     __shared__ int64_t srp[FILL_WAVES][TILE + 2];
     __shared__ int64_t sdel[FILL_WAVES][TILE + 1];
     if (!st->reordered) return;
-    const bool packed = st->packed != 0;
+    if (st->packed == PACK_GROUP) return;     // k_rl_fill_group builds it
+    const bool packed = st->packed == PACK_TILE;
     const int lane = threadIdx.x & 63;
     int64_t* s = srp[threadIdx.x >> 6];
     int64_t* d = sdel[threadIdx.x >> 6];
     const TileRange tr = wave_tiles<FILL_WAVES>(0, n_tiles);
     for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
-        const int64_t r_lo = ob[t], r_hi = ob[t + 1];
-        const int64_t t0 = t * TILE - r_lo;
-        const int cnt = (int)(min<int64_t>((t + 1) * TILE, nnz + n) - r_hi - t0);
-        if (cnt <= 0) continue;                   // row ends only: no entries to move
-        // Rows r_lo .. r_last touch the tile (at most TILE + 1 of them).
-        const int64_t r_last = min(r_hi, n - 1);
-        const int nr = (int)(r_last - r_lo + 1);
-        for (int i = lane; i <= nr; i += 64) s[i] = rp2[r_lo + i];
-        for (int i = lane; i < nr; i += 64) d[i] = rp[perm[r_lo + i]] - rp2[r_lo + i];
-        wave_sync();
-        int64_t src[TP];
-#pragma unroll
-        for (int e = 0; e < TP; ++e) {
-            const int64_t q = t0 + min(e * 64 + lane, cnt - 1);
-            // Largest i < nr with s[i] <= q (the row whose range holds q).
-            int lo = 0;
-#pragma unroll
-            for (int step = TILE; step > 0; step >>= 1)
-                if (lo + step < nr && s[lo + step] <= q) lo += step;
-            src[e] = q + d[lo];
-        }
         int32_t c[TP];
         VT v[TP];
-#pragma unroll
-        for (int e = 0; e < TP; ++e) {
-            c[e] = col[src[e]];
-            v[e] = val[src[e]];
-        }
-#pragma unroll
-        for (int e = 0; e < TP; ++e) c[e] = iperm[c[e]];
+        int64_t t0 = 0;
+        const int cnt = fill_tile_gather(t, rp, col, val, n, nnz, ob, perm, iperm, rp2, s, d, lane, &t0, c, v);
+        if (cnt <= 0) continue;                   // row ends only: no entries to move
         if (!packed) {
 #pragma unroll
             for (int e = 0; e < TP; ++e) {
@@ -401,7 +440,7 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
         uint32_t kr[TP];
 #pragma unroll
         for (int r = 0; r < TP; ++r) kr[r] = key[lane * TP + r];
-        sort_tile_keys(kr, lane);
+        sort_keys<TILE>(kr, lane, nullptr);
         wave_sync();
 #pragma unroll
         for (int r = 0; r < TP; ++r) key[lane * TP + r] = kr[r];
@@ -416,6 +455,75 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
             }
         }
         wave_sync();
+    }
+}
+
+// Group-sorted fill (n <= 2^20): a workgroup of GROUP_TILES wavefronts
+// takes a group of consecutive tiles; each wavefront gathers its tile as
+// above, the keys (col << 12 | position in the group) and values go to LDS
+// by position, the workgroup sorts the keys, and the sorted keys are stored
+// with their values.
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_rl_fill_group(const State* st, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                                         int64_t n, int64_t nnz, int64_t n_tiles,
+                                                         const int32_t* __restrict__ ob,
+                                                         const int32_t* __restrict__ perm,
+                                                         const int32_t* __restrict__ iperm,
+                                                         const int64_t* __restrict__ rp2, int32_t* __restrict__ col2,
+                                                         VT* __restrict__ val2) {
+    static_assert(BLOCK / 64 == GROUP_TILES, "one wavefront per tile of a group");
+    constexpr int GN = GROUP_TILES * TILE;
+    __shared__ int64_t srp[GROUP_TILES][TILE + 2];
+    __shared__ int64_t sdel[GROUP_TILES][TILE + 1];
+    static_assert(sizeof(srp) >= GN * sizeof(uint32_t) && sizeof(sdel) >= GN * sizeof(VT), "LDS reuse");
+    if (!st->reordered || st->packed != PACK_GROUP) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int64_t* s = srp[w];
+    int64_t* d = sdel[w];
+    uint32_t* key = reinterpret_cast<uint32_t*>(&srp[0][0]);
+    VT* sv = reinterpret_cast<VT*>(&sdel[0][0]);
+    const int64_t n_groups = (n_tiles + GROUP_TILES - 1) / GROUP_TILES;
+    const int64_t xcd = blockIdx.x & 7, nb8 = gridDim.x >> 3;
+    const int64_t lo = n_groups * xcd / 8, hi = n_groups * (xcd + 1) / 8;
+    for (int64_t g = lo + (blockIdx.x >> 3); g < hi; g += nb8) {
+        const int64_t tg = g * GROUP_TILES, te = min<int64_t>(tg + GROUP_TILES, n_tiles);
+        const int64_t g0 = tg * TILE - ob[tg];
+        const int64_t gend = te >= n_tiles ? nnz : te * TILE - ob[te];
+        const int ne = (int)(gend - g0);
+        const int64_t t = tg + w;
+        int32_t c[TP];
+        VT v[TP];
+        int64_t t0 = 0;
+        const int cnt = t < n_tiles ? fill_tile_gather(t, rp, col, val, n, nnz, ob, perm, iperm, rp2, s, d, lane,
+                                                       &t0, c, v)
+                                    : 0;
+        __syncthreads();                          // the key and value arrays overlap every wavefront's s, d
+        const int off = (int)(t0 - g0);
+#pragma unroll
+        for (int e = 0; e < TP; ++e) {
+            const int k = e * 64 + lane;
+            if (k < cnt) {
+                key[off + k] = ((uint32_t)c[e] << GROUP_SLOTBITS) | (uint32_t)(off + k);
+                sv[off + k] = v[e];
+            }
+        }
+        for (int p = ne + tid; p < GN; p += BLOCK) key[p] = 0xffffffffu;
+        __syncthreads();
+        uint32_t kr[TP];
+#pragma unroll
+        for (int r = 0; r < TP; ++r) kr[r] = key[tid * TP + r];
+        __syncthreads();
+        sort_keys<GN>(kr, tid, key);
+#pragma unroll
+        for (int r = 0; r < TP; ++r) key[tid * TP + r] = kr[r];
+        __syncthreads();
+        for (int p = tid; p < ne; p += BLOCK) {
+            const uint32_t kv = key[p];
+            col2[g0 + p] = (int32_t)kv;
+            val2[g0 + p] = sv[kv & GROUP_SLOTMASK];
+        }
+        __syncthreads();
     }
 }
 
@@ -482,6 +590,27 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
                 break;
             default:
                 hipLaunchKernelGGL(k_rl_fill<uint16_t>, dim3(p.g_tile * (WAVES / FILL_WAVES)), dim3(FILL_WAVES * 64), 0, s, b.st, a.rowptr, a.col,
+                                   (const uint16_t*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
+                                   (uint16_t*)b.val2);
+                break;
+        }
+        // Group-sorted copy (decided on the device; the kernel returns unless
+        // the state asks for it).
+        const int64_t n_groups = (p.n_tiles + GROUP_TILES - 1) / GROUP_TILES;
+        const int gg = (int)((std::min<int64_t>(n_groups, 4096) + 7) / 8 * 8);
+        switch (p.prec) {
+            case 0:
+                hipLaunchKernelGGL(k_rl_fill_group<double>, dim3(gg), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                                   (const double*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
+                                   (double*)b.val2);
+                break;
+            case 1:
+                hipLaunchKernelGGL(k_rl_fill_group<float>, dim3(gg), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
+                                   (const float*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
+                                   (float*)b.val2);
+                break;
+            default:
+                hipLaunchKernelGGL(k_rl_fill_group<uint16_t>, dim3(gg), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col,
                                    (const uint16_t*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
                                    (uint16_t*)b.val2);
                 break;

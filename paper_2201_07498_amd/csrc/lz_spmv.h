@@ -125,28 +125,183 @@ __device__ __forceinline__ double split_total(const double* head, const double* 
     return s + ld_dev(&head[t2]);
 }
 
-// NW wavefronts per workgroup; the grid walks tiles [tb, te) (tile indices
-// and the tables stay those of the whole matrix).  With CACHED, xs holds
-// x[0..hn) in LDS and gathers of those entries read it instead of global
-// memory.  With OFF32
+// The products of one wavefront's share of stored entries [base, base+cnt)
+// in LDS.  The 16 col/val loads of a lane go out together, then the 16
+// gathers of x.  Lanes past the end re-read the last entry (same cache line),
+// so every load is unconditional.  Row-ordered storage (slotbits = 0): entry
+// base+k lands in pw[k], and lanes past the end land beyond cnt, never read.
+// Column-sorted storage: each column word is (col << slotbits) | slot and the
+// product lands in pw[slot], the entry's position in row order, so the row
+// sums add the same values in the same order as for row-ordered storage
+// (lanes past the end rewrite the last entry's product).  With CACHED, xs
+// holds x[0..hn) in LDS and gathers of those entries read it.  With OFF32
 // (every byte offset into x below 2^32), each load is a wave-uniform base in
-// scalar registers plus a 32-bit per-lane offset, and the col and val loads of
-// an entry share one offset; 64-bit per-lane addresses would otherwise take
+// scalar registers plus a 32-bit per-lane offset, and the col and val loads
+// of an entry share one offset; 64-bit per-lane addresses would otherwise take
 // about half of the kernel's vector registers and limit its occupancy.
-// The row bounds of the first 64 owned rows, pre() of those rows and the
-// start of the row continuing past the tile are loaded with the tile's
-// entries, so a tile waits for two rounds of requests (entries, then
-// gathers) before its sums are written.
+template <class VT, class AT, bool CACHED, bool OFF32>
+__device__ __forceinline__ void tile_products(const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                              const VT* __restrict__ x, const VT* xs, int hn, int64_t base, int cnt,
+                                              int slotbits, AT* pw, int lane) {
+    if (cnt <= 0) return;
+    int ci[TP];
+    VT vv[TP];
+    if constexpr (OFF32) {
+        const char* cb = (const char*)(col + base);
+        const char* vb = (const char*)(val + base);
+#pragma unroll
+        for (int q = 0; q < TP; ++q) {
+            const uint32_t o = (uint32_t)min(q * 64 + lane, cnt - 1);
+            ci[q] = *(const int32_t*)(cb + o * 4u);
+            vv[q] = *(const VT*)(vb + o * (uint32_t)sizeof(VT));
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < TP; ++q) {
+            const int64_t p = base + min(q * 64 + lane, cnt - 1);
+            ci[q] = col[p];
+            vv[q] = val[p];
+        }
+    }
+    int sl[TP];
+    const uint32_t smask = (1u << slotbits) - 1u;
+#pragma unroll
+    for (int q = 0; q < TP; ++q) {
+        sl[q] = slotbits ? (int)((uint32_t)ci[q] & smask) : q * 64 + lane;
+        ci[q] = (int)((uint32_t)ci[q] >> slotbits);
+    }
+#pragma unroll
+    for (int q = 0; q < TP; ++q) {
+        VT xv;
+        if constexpr (CACHED)
+            xv = ci[q] < hn ? xs[ci[q]] : x[ci[q]];
+        else if constexpr (OFF32)
+            xv = *(const VT*)((const char*)x + (uint32_t)ci[q] * (uint32_t)sizeof(VT));
+        else
+            xv = x[ci[q]];
+        pw[sl[q]] = to_a(vv[q], AT(0)) * to_a(xv, AT(0));
+    }
+}
+
+// Row bounds of a tile's first 64 owned rows, pre() of those rows and the
+// start of the row continuing past the tile; loaded with the tile's entries,
+// so a tile waits for two rounds of requests (entries, then gathers) before
+// its sums are written.
+struct TileRows {
+    int64_t t, t0, r_lo, r_hi, rb0, re0, rb_hi;
+    double pv0;
+    int cnt;
+};
+template <class Pre>
+__device__ __forceinline__ TileRows tile_rows(const int64_t* __restrict__ rp, int64_t t, int64_t r_lo, int64_t r_hi,
+                                              int64_t n, int64_t items, int lane, Pre&& pre) {
+    TileRows q;
+    q.t = t;
+    q.r_lo = r_lo;
+    q.r_hi = r_hi;
+    q.t0 = t * TILE - r_lo;
+    q.cnt = (int)(min<int64_t>((t + 1) * TILE, items) - r_hi - q.t0);
+    const int64_t r_first = r_lo + lane;
+    q.rb0 = 0;
+    q.re0 = 0;
+    q.pv0 = 0.0;
+    if (r_first < r_hi) {
+        q.rb0 = rp[r_first];
+        q.re0 = rp[r_first + 1];
+        q.pv0 = pre(r_first);
+    }
+    q.rb_hi = r_hi < n ? rp[r_hi] : 0;
+    return q;
+}
+
+// Sums of one tile from its products pw[0..cnt) in row order: owned rows
+// (one lane each up to LONGR entries, else the whole wavefront), then the
+// head and tail pieces of split rows.
+template <class AT, class Pre, class Row, class Piece, class Fin>
+__device__ __forceinline__ void tile_sums(const TileRows& q, const AT* pw, const int64_t* __restrict__ rp, int64_t n,
+                                          int64_t n_tiles, uint32_t* tk, double* head, double* tail, int lane,
+                                          Pre&& pre, Row&& row, Piece&& piece, Fin&& fin) {
+    const int64_t t = q.t, t0 = q.t0, r_lo = q.r_lo, r_hi = q.r_hi;
+    const int cnt = q.cnt;
+    // Owned rows, 64 at a time.
+    const bool split_head = r_lo < r_hi && __shfl(q.rb0, 0, 64) < t0;
+    double head_s = 0.0;
+    for (int64_t base = r_lo; base < r_hi; base += 64) {
+        const int64_t r = base + lane;
+        const bool valid = r < r_hi;
+        const bool first = base == r_lo;
+        int b = 0, e = 0;
+        double pv = 0.0;
+        if (valid) {
+            b = (int)(max(first ? q.rb0 : rp[r], t0) - t0);
+            e = (int)((first ? q.re0 : rp[r + 1]) - t0);
+            pv = first ? q.pv0 : pre(r);
+        }
+        const bool islong = valid && e - b > LONGR;
+        AT s = (valid && !islong) ? lds_sum(pw, b, e) : AT(0);
+        uint64_t mask = __ballot(islong);
+        while (mask) {
+            const int L = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const AT ss = lds_wave_sum(pw, __shfl(b, L, 64), __shfl(e, L, 64), lane);
+            if (lane == L) s = ss;
+        }
+        if (valid) {
+            if (split_head && r == r_lo) {
+                head_s = (double)s;
+                piece(r, head_s);
+            } else {
+                row(r, (double)s, pv);
+            }
+        }
+    }
+    // Head piece: publish, count, finish the row if it is the last piece.
+    if (split_head) {
+        if (lane == 0) st_dev(&head[t], head_s);
+        const int64_t t1 = item_tile(rp[r_lo] + r_lo, n_tiles);
+        if (last_wave(&tk[t], (uint32_t)(t - t1 + 1))) {
+            const double tot = split_total(head, tail, t1, t, lane);
+            if (lane == 0) fin(r_lo, tot);
+        }
+    }
+    // Tail piece of the row that continues past this tile.
+    if (r_hi < n) {
+        const int64_t rb = q.rb_hi;
+        if (rb < t0 + cnt) {
+            const AT ss = lds_wave_sum(pw, (int)(max(rb, t0) - t0), cnt, lane);
+            if (lane == 0) {
+                piece(r_hi, (double)ss);
+                st_dev(&tail[t], (double)ss);
+            }
+            const int64_t t1 = item_tile(rb + r_hi, n_tiles), t2 = row_owner(rp, r_hi, n_tiles);
+            if (last_wave(&tk[t2], (uint32_t)(t2 - t1 + 1))) {
+                const double tot = split_total(head, tail, t1, t2, lane);
+                if (lane == 0) fin(r_hi, tot);
+            }
+        }
+    }
+}
+
+// The workgroup's product buffer: one TILE slice per wavefront, contiguous,
+// so a group of NW tiles has one row-ordered array of NW * TILE slots.
+template <class AT, int NW>
+__device__ __forceinline__ AT* prod_lds() {
+    __shared__ AT prod[NW * TILE];
+    return prod;
+}
+
+// Wavefront per tile over tiles [tb, te) (tile indices and the tables stay
+// those of the whole matrix); each wavefront walks its own tiles.
+// slotbits = PACK_SLOTBITS for tile-sorted storage, 0 for row order.
 template <class VT, class AT, int NW, bool CACHED, bool OFF32, class Pre, class Row, class Piece, class Fin>
 __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const VT* __restrict__ x, const VT* xs,
                                            int hn, int64_t n, int64_t nnz, int64_t n_tiles, int64_t tb,
-                                           int64_t te, bool packed, const int32_t* __restrict__ ob, uint32_t* tk,
+                                           int64_t te, int slotbits, const int32_t* __restrict__ ob, uint32_t* tk,
                                            double* head, double* tail, Pre&& pre, Row&& row, Piece&& piece,
                                            Fin&& fin) {
-    __shared__ AT prod[NW][TILE];
     const int lane = threadIdx.x & 63;
-    AT* pw = prod[threadIdx.x >> 6];
+    AT* pw = prod_lds<AT, NW>() + (threadIdx.x >> 6) * TILE;
     const TileRange tr = wave_tiles<NW>(tb, te);
     const int64_t items = nnz + n;
     int64_t r_lo = 0, r_hi = 0;
@@ -155,8 +310,6 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
         r_hi = ob[tr.first + 1];
     }
     for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
-        const int64_t t0 = t * TILE - r_lo;
-        const int cnt = (int)(min<int64_t>((t + 1) * TILE, items) - r_hi - t0);
         // Row bounds of the next tile, loaded while this one works.
         const int64_t tn = t + tr.stride;
         int64_t n_lo = 0, n_hi = 0;
@@ -164,123 +317,58 @@ __device__ __forceinline__ void spmv_tiles(const int64_t* __restrict__ rp, const
             n_lo = ob[tn];
             n_hi = ob[tn + 1];
         }
-        // Bounds and epilogue operands of the first 64 owned rows, and the
-        // start of the continuing row.
-        const int64_t r_first = r_lo + lane;
-        int64_t rb0 = 0, re0 = 0;
-        double pv0 = 0.0;
-        if (r_first < r_hi) {
-            rb0 = rp[r_first];
-            re0 = rp[r_first + 1];
-            pv0 = pre(r_first);
-        }
-        const int64_t rb_hi = r_hi < n ? rp[r_hi] : 0;
-        // Entries of the tile, then the gathers of x.  Lanes past the end
-        // re-read the tile's last entry (same cache line), so every load is
-        // unconditional; their products land beyond cnt and are never read
-        // (or, in a column-sorted tile, rewrite the last entry's product).
-        if (cnt > 0) {
-            int ci[TP];
-            VT vv[TP];
-            if constexpr (OFF32) {
-                const char* cb = (const char*)(col + t0);
-                const char* vb = (const char*)(val + t0);
-#pragma unroll
-                for (int q = 0; q < TP; ++q) {
-                    const uint32_t o = (uint32_t)min(q * 64 + lane, cnt - 1);
-                    ci[q] = *(const int32_t*)(cb + o * 4u);
-                    vv[q] = *(const VT*)(vb + o * (uint32_t)sizeof(VT));
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < TP; ++q) {
-                    const int64_t p = t0 + min(q * 64 + lane, cnt - 1);
-                    ci[q] = col[p];
-                    vv[q] = val[p];
-                }
-            }
-            // Column-sorted tiles: the product goes to the entry's position
-            // in row order, so the row sums below add the same values in the
-            // same order as for a tile stored in row order.
-            int sl[TP];
-#pragma unroll
-            for (int q = 0; q < TP; ++q) {
-                sl[q] = packed ? (int)((uint32_t)ci[q] & PACK_SLOTMASK) : q * 64 + lane;
-                ci[q] = packed ? (int)((uint32_t)ci[q] >> PACK_SLOTBITS) : ci[q];
-            }
-#pragma unroll
-            for (int q = 0; q < TP; ++q) {
-                VT xv;
-                if constexpr (CACHED)
-                    xv = ci[q] < hn ? xs[ci[q]] : x[ci[q]];
-                else if constexpr (OFF32)
-                    xv = *(const VT*)((const char*)x + (uint32_t)ci[q] * (uint32_t)sizeof(VT));
-                else
-                    xv = x[ci[q]];
-                pw[sl[q]] = to_a(vv[q], AT(0)) * to_a(xv, AT(0));
-            }
-        }
+        const TileRows q = tile_rows(rp, t, r_lo, r_hi, n, items, lane, pre);
+        tile_products<VT, AT, CACHED, OFF32>(col, val, x, xs, hn, q.t0, q.cnt, slotbits, pw, lane);
         wave_sync();
-        // Owned rows, 64 at a time.
-        const bool split_head = r_lo < r_hi && __shfl(rb0, 0, 64) < t0;
-        double head_s = 0.0;
-        for (int64_t base = r_lo; base < r_hi; base += 64) {
-            const int64_t r = base + lane;
-            const bool valid = r < r_hi;
-            const bool first = base == r_lo;
-            int b = 0, e = 0;
-            double pv = 0.0;
-            if (valid) {
-                b = (int)(max(first ? rb0 : rp[r], t0) - t0);
-                e = (int)((first ? re0 : rp[r + 1]) - t0);
-                pv = first ? pv0 : pre(r);
-            }
-            const bool islong = valid && e - b > LONGR;
-            AT s = (valid && !islong) ? lds_sum(pw, b, e) : AT(0);
-            uint64_t mask = __ballot(islong);
-            while (mask) {
-                const int L = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                const AT ss = lds_wave_sum(pw, __shfl(b, L, 64), __shfl(e, L, 64), lane);
-                if (lane == L) s = ss;
-            }
-            if (valid) {
-                if (split_head && r == r_lo) {
-                    head_s = (double)s;
-                    piece(r, head_s);
-                } else {
-                    row(r, (double)s, pv);
-                }
-            }
-        }
-        // Head piece: publish, count, finish the row if it is the last piece.
-        if (split_head) {
-            if (lane == 0) st_dev(&head[t], head_s);
-            const int64_t t1 = item_tile(rp[r_lo] + r_lo, n_tiles);
-            if (last_wave(&tk[t], (uint32_t)(t - t1 + 1))) {
-                const double tot = split_total(head, tail, t1, t, lane);
-                if (lane == 0) fin(r_lo, tot);
-            }
-        }
-        // Tail piece of the row that continues past this tile.
-        if (r_hi < n) {
-            const int64_t rb = rb_hi;
-            if (rb < t0 + cnt) {
-                const AT ss = lds_wave_sum(pw, (int)(max(rb, t0) - t0), cnt, lane);
-                if (lane == 0) {
-                    piece(r_hi, (double)ss);
-                    st_dev(&tail[t], (double)ss);
-                }
-                const int64_t t1 = item_tile(rb + r_hi, n_tiles), t2 = row_owner(rp, r_hi, n_tiles);
-                if (last_wave(&tk[t2], (uint32_t)(t2 - t1 + 1))) {
-                    const double tot = split_total(head, tail, t1, t2, lane);
-                    if (lane == 0) fin(r_hi, tot);
-                }
-            }
-        }
+        tile_sums(q, pw, rp, n, n_tiles, tk, head, tail, lane, pre, row, piece, fin);
         wave_sync();
         r_lo = n_lo;
         r_hi = n_hi;
+    }
+}
+
+// Group-sorted storage: the entries of each group of GROUP_TILES consecutive
+// tiles are stored in column order with GROUP_SLOTBITS-bit slots (positions
+// in the group's row order).  A workgroup takes NW / GROUP_TILES groups at a
+// time; wavefront w loads the (w % GROUP_TILES)-th TILE of its group's stored
+// entries, so one wavefront instruction gathers from a narrow column range.
+// The products land in the group's row-ordered slice of the workgroup buffer,
+// and after a barrier each wavefront sums its own tile.  Group sets are split
+// contiguously over the eight XCDs.  Every wavefront runs the same number of
+// iterations (the barriers need it).
+template <class VT, class AT, int NW, bool CACHED, bool OFF32, class Pre, class Row, class Piece, class Fin>
+__device__ __forceinline__ void spmv_groups(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                            const VT* __restrict__ val, const VT* __restrict__ x, const VT* xs,
+                                            int hn, int64_t n, int64_t nnz, int64_t n_tiles,
+                                            const int32_t* __restrict__ ob, uint32_t* tk, double* head,
+                                            double* tail, Pre&& pre, Row&& row, Piece&& piece, Fin&& fin) {
+    static_assert(NW % GROUP_TILES == 0, "whole groups per workgroup");
+    constexpr int GPW = NW / GROUP_TILES;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wi = w % GROUP_TILES;
+    AT* pg = prod_lds<AT, NW>() + (w / GROUP_TILES) * (GROUP_TILES * TILE);
+    const int64_t items = nnz + n;
+    const int64_t n_groups = (n_tiles + GROUP_TILES - 1) / GROUP_TILES;
+    const int64_t n_sets = (n_groups + GPW - 1) / GPW;
+    const int64_t xcd = blockIdx.x & 7, nb8 = gridDim.x >> 3;
+    const int64_t lo = n_sets * xcd / 8, hi = n_sets * (xcd + 1) / 8;
+    for (int64_t gs = lo + (blockIdx.x >> 3); gs < hi; gs += nb8) {
+        const int64_t tg = (gs * GPW + w / GROUP_TILES) * GROUP_TILES;
+        const bool live = tg < n_tiles;
+        const int64_t te = min<int64_t>(tg + GROUP_TILES, n_tiles);
+        const int64_t g0 = live ? tg * TILE - ob[tg] : nnz;
+        const int64_t gend = !live || te >= n_tiles ? nnz : te * TILE - ob[te];
+        const int64_t t = tg + wi;
+        const bool has = t < n_tiles;
+        TileRows q{};
+        if (has) q = tile_rows(rp, t, ob[t], ob[t + 1], n, items, lane, pre);
+        const int cw = (int)max<int64_t>(0, min<int64_t>(TILE, gend - g0 - (int64_t)wi * TILE));
+        tile_products<VT, AT, CACHED, OFF32>(col, val, x, xs, hn, g0 + (int64_t)wi * TILE, cw, GROUP_SLOTBITS, pg,
+                                              lane);
+        __syncthreads();
+        if (has) tile_sums(q, pg + (q.t0 - g0), rp, n, n_tiles, tk, head, tail, lane, pre, row, piece, fin);
+        __syncthreads();
     }
 }
 

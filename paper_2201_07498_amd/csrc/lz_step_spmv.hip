@@ -97,8 +97,14 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
         for (int i = threadIdx.x; i < hn; i += NW * 64) xs[i] = x[i];
         __syncthreads();
     }
-    spmv_tiles<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, tb, te, rl && st->packed != 0,
-                                          ob, tk, head, tail, pre, row, piece, fin);
+    const int packing = rl ? st->packed : PACK_NONE;
+    if (packing == PACK_GROUP)
+        spmv_groups<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, pre,
+                                               row, piece, fin);
+    else
+        spmv_tiles<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, tb, te,
+                                              packing == PACK_TILE ? PACK_SLOTBITS : 0, ob, tk, head, tail, pre,
+                                              row, piece, fin);
     if (!need_alpha) return;
     apart = block_sum(apart, shd, NW);
     if (threadIdx.x == 0) st_dev(&part[(int64_t)slab * gridDim.x + blockIdx.x], (double)apart);
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_plain(State* st, const int64_t* 
     using WT = typename Tr<P>::W;
     if (st->status != 0) return;
     spmv_tiles<VT, AT, WAVES, false, false>(
-        rp, col, val, x, nullptr, 0, n, nnz, n_tiles, 0, n_tiles, false, ob, tk, head, tail,
+        rp, col, val, x, nullptr, 0, n, nnz, n_tiles, 0, n_tiles, 0, ob, tk, head, tail,
         [](int64_t) { return 0.0; },
         [&](int64_t r, double acc, double) { y[r] = (WT)acc; }, [&](int64_t, double) {},
         [&](int64_t r, double acc) { y[r] = (WT)acc; });

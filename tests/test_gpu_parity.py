@@ -391,3 +391,22 @@ def test_report_metrics_match_oracle_definitions():
     ab, rel = oracle.residuals(rp, c, v, vals, Y)
     np.testing.assert_allclose(rep["abs_resid"], ab, rtol=1e-9, atol=1e-14)
     np.testing.assert_allclose(rep["resid"], rel, rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_relabelled_between_2e20_and_2e22_rows_matches_caller_order(precision):
+    # 2^20 < n < 2^22: the relabelled copy stores each tile column-sorted
+    # (smaller matrices use groups of four tiles).  The solve on P A P^T
+    # follows the caller-order solve up to rounding.
+    rp, c, v = synth.rmat(21, 4, seed=5)
+    n = rp.size - 1
+    assert (1 << 20) < n < (1 << 22)
+    K, m = 4, 16
+    drp, dc, dv = device_csr(rp, c, v, precision)
+    a = lz.topk(drp, dc, dv, K, m, precision, seed=2, reorder="hubs")
+    b = lz.topk(drp, dc, dv, K, m, precision, seed=2, reorder="off")
+    torch.cuda.synchronize()
+    assert a[2]["reordered"] and not b[2]["reordered"]
+    err = eig_rel_err(a[0].cpu().numpy(), b[0].cpu().numpy())
+    print(f"rmat21 {precision}: hub-first vs caller order eig rel err {err:.2e}")
+    assert err <= (1e-9 if precision == "fp64" else 1e-5)
