@@ -60,6 +60,24 @@ def test_rmat20_fp64_and_fp32_match_oracle(rmat20):
     np.testing.assert_allclose(rep64["abs_resid"], ref["abs_resid"], rtol=1e-5, atol=1e-12)
 
 
+def test_rmat20_bf16_matches_oracle(rmat20):
+    # BF16 storage at n = 2^20, relabelled: the Lanczos-step SpMV runs its
+    # LDS-cached variant over group-sorted storage.  Oracle on the same
+    # BF16-rounded matrix; eigenvalues the oracle has converged agree to the
+    # BF16 tolerance.
+    rp, c, v = rmat20
+    v = synth.round_values(v, "bf16")
+    K, m = 16, 48
+    ref = oracle.topk(rp, c, v, K, m, seed=0)
+    vb, Yb, repb = solve(rp, c, v, K, m, "bf16")
+    conv = ref["rel_resid"] < 1e-6
+    err = np.abs(vb - ref["vals"]) / np.abs(ref["vals"])
+    print(f"bf16 rmat20: {conv.sum()} converged, max rel err there {err[conv].max():.2e}, all {err.max():.2e}")
+    assert repb["reordered"]
+    assert conv.sum() >= 4
+    assert err[conv].max() <= 1e-3
+
+
 @pytest.fixture(scope="module")
 def rmat23():
     rp, c, v = synth.rmat(23, 16, seed=0)
