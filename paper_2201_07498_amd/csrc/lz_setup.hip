@@ -344,15 +344,16 @@ __device__ __forceinline__ void sort_keys(uint32_t (&kr)[TP], int tid, uint32_t*
 
 // One wavefront's share of the fill: the 16 entries of each lane of tile t
 // (entry t0 + e*64 + lane, clamped to the tile) with columns relabelled.  The
-// tile's rows are staged in s/d first: their first new position and the shift
-// from new to old position (rp[perm[row]] - rp2[row]).  Returns the tile's
-// entry count (0: row ends only, nothing loaded).
+// tile's rows are staged in s/d first: their first new position relative to
+// the tile (clamped at -1: only the first row can start before it) and the
+// shift from new to old position (rp[perm[row]] - rp2[row]).  Returns the
+// tile's entry count (0: row ends only, nothing loaded).
 template <class VT>
 __device__ __forceinline__ int fill_tile_gather(int64_t t, const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col, const VT* __restrict__ val,
                                                 int64_t n, int64_t nnz, const int32_t* __restrict__ ob,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
-                                                const int64_t* __restrict__ rp2, int64_t* s, int64_t* d, int lane,
+                                                const int64_t* __restrict__ rp2, int32_t* s, int64_t* d, int lane,
                                                 int64_t* t0_out, int32_t (&c)[TP], VT (&v)[TP]) {
     const int64_t r_lo = ob[t], r_hi = ob[t + 1];
     const int64_t t0 = t * TILE - r_lo;
@@ -362,19 +363,19 @@ __device__ __forceinline__ int fill_tile_gather(int64_t t, const int64_t* __rest
     // Rows r_lo .. r_last touch the tile (at most TILE + 1 of them).
     const int64_t r_last = min(r_hi, n - 1);
     const int nr = (int)(r_last - r_lo + 1);
-    for (int i = lane; i <= nr; i += 64) s[i] = rp2[r_lo + i];
+    for (int i = lane; i <= nr; i += 64) s[i] = (int32_t)max<int64_t>(rp2[r_lo + i] - t0, -1);
     for (int i = lane; i < nr; i += 64) d[i] = rp[perm[r_lo + i]] - rp2[r_lo + i];
     wave_sync();
     int64_t src[TP];
 #pragma unroll
     for (int e = 0; e < TP; ++e) {
-        const int64_t q = t0 + min(e * 64 + lane, cnt - 1);
-        // Largest i < nr with s[i] <= q (the row whose range holds q).
+        const int k = min(e * 64 + lane, cnt - 1);
+        // Largest i < nr with s[i] <= k (the row whose range holds entry t0 + k).
         int lo = 0;
 #pragma unroll
         for (int step = TILE; step > 0; step >>= 1)
-            if (lo + step < nr && s[lo + step] <= q) lo += step;
-        src[e] = q + d[lo];
+            if (lo + step < nr && s[lo + step] <= k) lo += step;
+        src[e] = t0 + k + d[lo];
     }
 #pragma unroll
     for (int e = 0; e < TP; ++e) {
@@ -395,13 +396,13 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
                                                             const int32_t* __restrict__ iperm,
                                                             const int64_t* __restrict__ rp2,
                                                             int32_t* __restrict__ col2, VT* __restrict__ val2) {
-    __shared__ int64_t srp[FILL_WAVES][TILE + 2];
+    __shared__ int32_t srp[FILL_WAVES][TILE + 2];
     __shared__ int64_t sdel[FILL_WAVES][TILE + 1];
     if (!st->reordered) return;
     if (st->packed == PACK_GROUP) return;     // k_rl_fill_group builds it
     const bool packed = st->packed == PACK_TILE;
     const int lane = threadIdx.x & 63;
-    int64_t* s = srp[threadIdx.x >> 6];
+    int32_t* s = srp[threadIdx.x >> 6];
     int64_t* d = sdel[threadIdx.x >> 6];
     const TileRange tr = wave_tiles<FILL_WAVES>(0, n_tiles);
     for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
@@ -474,12 +475,12 @@ __global__ __launch_bounds__(BLOCK) void k_rl_fill_group(const State* st, const 
                                                          VT* __restrict__ val2) {
     static_assert(BLOCK / 64 == GROUP_TILES, "one wavefront per tile of a group");
     constexpr int GN = GROUP_TILES * TILE;
-    __shared__ int64_t srp[GROUP_TILES][TILE + 2];
+    __shared__ int32_t srp[GROUP_TILES][TILE + 2];
     __shared__ int64_t sdel[GROUP_TILES][TILE + 1];
     static_assert(sizeof(srp) >= GN * sizeof(uint32_t) && sizeof(sdel) >= GN * sizeof(VT), "LDS reuse");
     if (!st->reordered || st->packed != PACK_GROUP) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    int64_t* s = srp[w];
+    int32_t* s = srp[w];
     int64_t* d = sdel[w];
     uint32_t* key = reinterpret_cast<uint32_t*>(&srp[0][0]);
     VT* sv = reinterpret_cast<VT*>(&sdel[0][0]);
