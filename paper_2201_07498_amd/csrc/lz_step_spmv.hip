@@ -163,9 +163,11 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
     {
         // FP32/BF16 storage: one resident set of workgroups (5 wavefronts per
         // SIMD, 256 CUs), each walking its share, so no late workgroups form
-        // a tail (R-MAT 20 FP32: 80.1 -> 76.7 us).  FP64 keeps the larger
-        // grid: its resident set (4 per SIMD) measured 4% slower.
-        const int g = P == 0 ? p.g_tile : std::min(p.g_tile, 5 * 256);
+        // a tail (R-MAT 20 FP32: 80.1 -> 76.7 us).  FP64 does better the
+        // other way, with one workgroup per four tiles up to 4096 (R-MAT 20:
+        // 1024 -> 110.0 us, 2048 -> 106.8 us, 4096 -> 102.7 us).
+        const int64_t g64 = std::min<int64_t>(4096, (p.n_tiles + 3) / 4);
+        const int g = P == 0 ? (int)((g64 + 7) / 8 * 8) : std::min(p.g_tile, 5 * 256);
         if (off32)
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(g), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
