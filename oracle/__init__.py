@@ -71,6 +71,12 @@ def _load():
         lib.orc_ortho_loss.argtypes = [i64, i32, P]
         lib.orc_mean_angle_deg.restype = f64
         lib.orc_mean_angle_deg.argtypes = [i64, i32, P]
+        lib.orc_round_bits.restype = f64
+        lib.orc_round_bits.argtypes = [f64, i32]
+        lib.orc_spmv_emul.restype = None
+        lib.orc_spmv_emul.argtypes = [i64, P, P, P, P, P, i32]
+        lib.orc_lanczos_emul.restype = i32
+        lib.orc_lanczos_emul.argtypes = [i64, P, P, P, i32, u64, i32, f64, i32, i32, i32, P, P, P]
         _lib = lib
     return _lib
 
@@ -120,6 +126,45 @@ def lanczos(rowptr, col, val, m: int, seed: int = 0, passes: int = 2,
                              passes, unit_roundoff, _p(alpha), _p(beta), _p(V))
     if rc < 0:
         raise ValueError(f"oracle lanczos failed with code {rc}")
+    return alpha, beta, V.T, rc
+
+
+# Significant bits of the emulated formats: (stored vectors, SpMV
+# accumulation, working vector).  "fp32" and "bf16" are the storage modes of
+# Sec. III-A with a binary32 accumulator; "fp64" rounds nothing.
+EMULATION = {"fp64": (53, 53, 53), "fp32": (24, 24, 24), "bf16": (8, 24, 24)}
+
+
+def round_bits(x: float, bits: int) -> float:
+    """x rounded to `bits` significant bits, ties to even (24: binary32,
+    8: bfloat16, in their normal ranges)."""
+    return float(_load().orc_round_bits(float(x), int(bits)))
+
+
+def spmv_emul(rowptr, col, val, x, acc_bits: int) -> np.ndarray:
+    """y = M x with products and partial sums rounded to acc_bits."""
+    rowptr, col, val = _csr(rowptr, col, val)
+    n = rowptr.size - 1
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(n, dtype=np.float64)
+    _load().orc_spmv_emul(n, _p(rowptr), _p(col), _p(val), _p(x), _p(y), int(acc_bits))
+    return y
+
+
+def lanczos_emul(rowptr, col, val, m: int, emulate: str, seed: int = 0, passes: int = 2,
+                 unit_roundoff: float = 2.0 ** -53):
+    """Algorithm 1 with the roundings of a reduced-precision storage mode
+    (EMULATION[emulate]); same outputs as lanczos()."""
+    store, acc, work = EMULATION[emulate]
+    rowptr, col, val = _csr(rowptr, col, val)
+    n = rowptr.size - 1
+    alpha = np.zeros(m, dtype=np.float64)
+    beta = np.zeros(m + 1, dtype=np.float64)
+    V = np.zeros((m + 1, n), dtype=np.float64)
+    rc = _load().orc_lanczos_emul(n, _p(rowptr), _p(col), _p(val), m, seed & (2 ** 64 - 1), passes,
+                                  unit_roundoff, store, acc, work, _p(alpha), _p(beta), _p(V))
+    if rc < 0:
+        raise ValueError(f"oracle lanczos_emul failed with code {rc}")
     return alpha, beta, V.T, rc
 
 
@@ -186,11 +231,17 @@ def mean_angle_deg(Y) -> float:
 
 
 def topk(rowptr, col, val, K: int, m: int, seed: int = 0, passes: int = 2,
-         unit_roundoff: float = 2.0 ** -53, report: bool = True) -> dict:
-    """The whole solve: Lanczos, Jacobi on T, Top-K, Ritz vectors, report."""
+         unit_roundoff: float = 2.0 ** -53, report: bool = True, emulate: str | None = None) -> dict:
+    """The whole solve: Lanczos, Jacobi on T, Top-K, Ritz vectors, report.
+    With `emulate` ("fp32", "bf16") the Lanczos phase rounds its stored
+    vectors and SpMV as that storage mode does (lanczos_emul); the rest is
+    binary64 either way."""
     if not (1 <= K <= m <= rowptr.size - 1):
         raise ValueError("need 1 <= K <= m <= n")
-    alpha, beta, V, restarts = lanczos(rowptr, col, val, m, seed, passes, unit_roundoff)
+    if emulate is None:
+        alpha, beta, V, restarts = lanczos(rowptr, col, val, m, seed, passes, unit_roundoff)
+    else:
+        alpha, beta, V, restarts = lanczos_emul(rowptr, col, val, m, emulate, seed, passes, unit_roundoff)
     T = tridiag(alpha, beta)
     theta, S, sweeps = jacobi(T)
     idx = select_topk(theta, K)

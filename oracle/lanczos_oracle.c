@@ -284,7 +284,7 @@ void orc_ritz(int64_t n, int m, const double *V, const double *S, int K,
 /*
  * Accuracy report (Sec. IV-D): for each Ritz pair the absolute residual
  * ||M y - theta y|| (the paper's L2 reconstruction error) and the relative
- * one, divided by |theta|.
+ * one, divided by |theta| (equal to the absolute one when theta = 0).
  */
 void orc_residuals(int64_t n, const int64_t *rowptr, const int32_t *col,
                    const double *val, int K, const double *vals, const double *Y,
@@ -300,7 +300,9 @@ void orc_residuals(int64_t n, const int64_t *rowptr, const int32_t *col,
             s += d * d;
         }
         abs_resid[k] = sqrt(s);
-        rel_resid[k] = sqrt(s) / fabs(vals[k]);
+        /* Relative to |theta|; an exact zero Ritz value has no scale, so its
+         * relative residual is the absolute one. */
+        rel_resid[k] = vals[k] != 0.0 ? sqrt(s) / fabs(vals[k]) : sqrt(s);
     }
     free(t);
 }
@@ -333,4 +335,119 @@ double orc_mean_angle_deg(int64_t n, int K, const double *Y)
             ++cnt;
         }
     return s / cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Precision emulation (Sec. III-A: vectors stored in a narrower format than
+ * the arithmetic).  Not part of the FP64 definition above: it re-runs
+ * Algorithm 1 with the stored quantities rounded, to predict how much a
+ * reduced storage precision moves the results, so that precision loss can be
+ * told apart from implementation errors.                                   */
+
+/* x rounded to the nearest number with `bits` significant bits (ties to the
+ * even significand).  bits >= 53 returns x; 24 gives the binary32 value and
+ * 8 the bfloat16 value of a double in their normal ranges. */
+double orc_round_bits(double x, int bits)
+{
+    if (bits >= 53 || x == 0.0 || !isfinite(x)) return x;
+    int e;
+    double f = frexp(x, &e);                  /* x = f * 2^e, 0.5 <= |f| < 1 */
+    double sig = ldexp(f, bits);              /* |sig| in [2^(bits-1), 2^bits) */
+    double r = floor(sig);
+    double d = sig - r;
+    if (d > 0.5 || (d == 0.5 && fmod(r, 2.0) != 0.0)) r += 1.0;
+    return ldexp(r, e - bits);
+}
+
+/* y = M x with every product and every partial sum rounded to acc_bits
+ * (the SpMV of a reduced-precision accumulator), rows summed in entry
+ * order. */
+void orc_spmv_emul(int64_t n, const int64_t *rowptr, const int32_t *col,
+                   const double *val, const double *x, double *y, int acc_bits)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        double s = 0.0;
+        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+            s = orc_round_bits(s + orc_round_bits(val[k] * x[col[k]], acc_bits), acc_bits);
+        y[r] = s;
+    }
+}
+
+/* v = round(w) / ||round(w)||: a Lanczos vector as stored in the basis
+ * precision, scaled to unit length in binary64.  Returns ||round(w)||. */
+static double store_unit(int64_t n, const double *w, double *v, int store_bits)
+{
+    for (int64_t r = 0; r < n; ++r) v[r] = orc_round_bits(w[r], store_bits);
+    double b = nrm2(n, v);
+    if (b > 0.0)
+        for (int64_t r = 0; r < n; ++r) v[r] /= b;
+    return b;
+}
+
+/*
+ * Algorithm 1 as orc_lanczos, with three roundings a mixed-precision run
+ * applies: every Lanczos vector is stored rounded to store_bits (then used
+ * at unit length), the SpMV products and sums are rounded to acc_bits, and
+ * its output is held in a working vector rounded to work_bits.  The dots,
+ * the three-term update and the Gram-Schmidt passes stay binary64.  With
+ * all three >= 53 every rounding is the identity and the results equal
+ * orc_lanczos bit for bit.  Same arguments, outputs and return codes.
+ */
+int orc_lanczos_emul(int64_t n, const int64_t *rowptr, const int32_t *col,
+                     const double *val, int m, uint64_t seed, int passes,
+                     double unit_roundoff, int store_bits, int acc_bits, int work_bits,
+                     double *alpha, double *beta, double *V)
+{
+    if (n < 1 || m < 1 || m > n || passes < 0 || !alpha || !beta || !V) return -1;
+    double *vt = (double *)malloc(sizeof(double) * (size_t)n);
+    double *vn = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!vt || !vn) { free(vt); free(vn); return -1; }
+
+    int restarts = 0;
+    double tnorm = 0.0;
+
+    for (int64_t r = 0; r < n; ++r) vn[r] = orc_u01(seed, (uint64_t)r);
+    store_unit(n, vn, V, store_bits);                          /* v_1 */
+    beta[0] = 0.0;
+
+    for (int i = 1; i <= m; ++i) {
+        double *vi = V + (int64_t)(i - 1) * n;
+        if (i != 1) {
+            double *tmp = vt;                  /* stored candidate for v_i */
+            for (int64_t r = 0; r < n; ++r) tmp[r] = orc_round_bits(vn[r], store_bits);
+            double b = nrm2(n, tmp);
+            double tau = 100.0 * unit_roundoff * tnorm;
+            if (!(b > tau)) {
+                ++restarts;
+                uint64_t rs = seed + ((uint64_t)restarts << 32);
+                for (int64_t r = 0; r < n; ++r) vn[r] = orc_u01(rs, (uint64_t)r);
+                mgs(n, V, i - 1, vn, 2);
+                double bn = store_unit(n, vn, vi, store_bits);
+                if (!(bn > 0.0)) { free(vt); free(vn); return -2; }
+                beta[i - 1] = 0.0;
+            } else {
+                beta[i - 1] = b;
+                for (int64_t r = 0; r < n; ++r) vi[r] = tmp[r] / b;
+            }
+        }
+        orc_spmv_emul(n, rowptr, col, val, vi, vt, acc_bits);    /* v_t = M v_i */
+        for (int64_t r = 0; r < n; ++r) vt[r] = orc_round_bits(vt[r], work_bits);
+        double a = dot(n, vi, vt);
+        alpha[i - 1] = a;
+        const double *vprev = (i >= 2) ? V + (int64_t)(i - 2) * n : NULL;
+        double bi = beta[i - 1];
+        for (int64_t r = 0; r < n; ++r)
+            vn[r] = vt[r] - a * vi[r] - (vprev ? bi * vprev[r] : 0.0);
+        mgs(n, V, i, vn, passes);
+        double t = fabs(a) + bi;
+        if (t > tnorm) tnorm = t;
+    }
+    double *vl = V + (int64_t)m * n;
+    double bl = store_unit(n, vn, vl, store_bits);
+    beta[m] = bl;
+    if (!(bl > 0.0))
+        for (int64_t r = 0; r < n; ++r) vl[r] = 0.0;
+    free(vt);
+    free(vn);
+    return restarts;
 }

@@ -298,3 +298,127 @@ def test_restart_keeps_basis_orthonormal_and_t_block_diagonal():
     zero_beta = np.nonzero(beta[1:9] == 0.0)[0]
     assert zero_beta.size == restarts
     assert np.max(np.abs(V[:, :9].T @ V[:, :9] - np.eye(9))) < 1e-13
+
+
+# ------------------------------------------------------ accuracy metrics
+@pytest.mark.parametrize("phi_deg", [90.0, 60.0, 30.0, 1.0, 120.0])
+def test_ortho_loss_and_mean_angle_of_two_vectors_at_a_known_angle(phi_deg):
+    # Sec. IV-D metrics on constructed vectors: two unit vectors at angle phi
+    # have X^T X - I = [[0, cos phi], [cos phi, 0]], so the loss is |cos phi|,
+    # and the angle between the lines they span is min(phi, 180 - phi).
+    phi = math.radians(phi_deg)
+    n = 7
+    X = np.zeros((n, 2))
+    X[2, 0] = 1.0
+    X[2, 1], X[5, 1] = math.cos(phi), math.sin(phi)
+    assert abs(oracle.ortho_loss(X) - abs(math.cos(phi))) <= 4 * EPS
+    assert abs(oracle.mean_angle_deg(X) - min(phi_deg, 180.0 - phi_deg)) <= 1e-9
+
+
+def test_mean_angle_averages_pairs_and_ortho_loss_sees_norms():
+    # e1, e2 and (e1 + e2)/sqrt(2): pair angles 90, 45, 45 -> mean 60.
+    X = np.zeros((4, 3))
+    X[0, 0] = 1.0
+    X[1, 1] = 1.0
+    X[0, 2] = X[1, 2] = 1.0 / math.sqrt(2.0)
+    assert abs(oracle.mean_angle_deg(X) - 60.0) <= 1e-9
+    assert abs(oracle.ortho_loss(X) - 1.0 / math.sqrt(2.0)) <= 4 * EPS
+    # A column of norm 2 has |x.x - 1| = 3; orthogonal columns lose nothing.
+    Y = np.zeros((5, 2))
+    Y[1, 0] = 2.0
+    Y[3, 1] = 1.0
+    assert oracle.ortho_loss(Y) == 3.0
+    assert oracle.mean_angle_deg(Y) == 90.0
+    assert oracle.mean_angle_deg(Y[:, :1]) == 90.0     # a single vector has no pairs
+
+
+def test_relative_residual_of_a_zero_ritz_value_is_the_absolute_one():
+    # Sec. IV-D residuals: relative to |theta|, and equal to the absolute
+    # residual when theta is exactly zero (no division by zero).
+    rp, c, v = synth.path(5)
+    y = np.array([1.0, 0.0, 0.0, 0.0, 0.0])[:, None]
+    ab, rel = oracle.residuals(rp, c, v, np.array([0.0]), y)
+    # A e_0 = e_1, so ||A y - 0 y|| = 1.
+    assert ab[0] == 1.0 and rel[0] == 1.0
+    ab2, rel2 = oracle.residuals(rp, c, v, np.array([2.0]), y)
+    assert ab2[0] == math.sqrt(5.0) and rel2[0] == math.sqrt(5.0) / 2.0
+
+
+# ------------------------------------------------------ precision emulation
+def test_round_bits_24_is_the_binary32_conversion():
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(2000) * 10.0 ** rng.integers(-20, 20, 2000)
+    want = x.astype(np.float32).astype(np.float64)
+    got = np.array([oracle.round_bits(t, 24) for t in x])
+    assert np.array_equal(got, want)
+    assert oracle.round_bits(0.1, 53) == 0.1
+
+
+def test_round_bits_8_is_bfloat16_nearest_even():
+    one = 1.0
+    ulp = 2.0 ** -7                         # bfloat16 spacing in [1, 2)
+    cases = [(one + ulp / 2, one),                       # tie -> even (1.0)
+             (one + 1.5 * ulp, one + 2 * ulp),           # tie -> even (odd neighbour below)
+             (one + ulp / 2 + 2.0 ** -30, one + ulp),    # just above the tie
+             (-(one + ulp / 2 + 2.0 ** -30), -(one + ulp)),
+             (3.0 * 2.0 ** -40, 3.0 * 2.0 ** -40),       # exactly representable
+             (255.5, 256.0)]                             # 8 significant bits: 255.5 is a tie, 256 even
+    for x, want in cases:
+        assert oracle.round_bits(x, 8) == want, x
+    # Against the input module's binary32 -> bfloat16 bit conversion, on
+    # values that are binary32 numbers (no double rounding involved).
+    rng = np.random.default_rng(12)
+    x32 = (rng.standard_normal(3000) * 10.0 ** rng.integers(-8, 8, 3000)).astype(np.float32)
+    want = synth.bf16_bits_to_f64(synth.f32_to_bf16_bits(x32))
+    got = np.array([oracle.round_bits(float(t), 8) for t in x32])
+    assert np.array_equal(got, want)
+
+
+def test_spmv_emul_accumulates_in_the_given_precision():
+    # Row 0: 1 + 2^-30 - 1.  In binary64 the sum is 2^-30; a binary32
+    # accumulator absorbs 2^-30 into 1 and returns 0.  Row 1 checks that the
+    # products are rounded too: (1 + 2^-30) * 1 -> 1 in binary32.
+    rowptr = np.array([0, 3, 4], np.int64)
+    col = np.array([0, 1, 0, 1], np.int32)
+    val = np.array([1.0, 2.0 ** -30, -1.0, 1.0 + 2.0 ** -30])
+    x = np.array([1.0, 1.0])
+    y53 = oracle.spmv_emul(rowptr, col, val, x, 53)
+    y24 = oracle.spmv_emul(rowptr, col, val, x, 24)
+    assert np.array_equal(y53, oracle.spmv(rowptr, col, val, x))
+    assert y53[0] == 2.0 ** -30 and y24[0] == 0.0
+    assert y53[1] == 1.0 + 2.0 ** -30 and y24[1] == 1.0
+
+
+@pytest.mark.parametrize("gen", ["er", "rmat", "cycle"])
+def test_lanczos_emul_without_rounding_is_the_oracle(gen):
+    if gen == "er":
+        rp, c, v = synth.er(700, 9.0, seed=4)
+    elif gen == "rmat":
+        rp, c, v = synth.rmat(10, 8, seed=4)
+    else:
+        rp, c, v = synth.cycle(40)            # double eigenvalues: restarts
+    m = 30
+    a1, b1, V1, r1 = oracle.lanczos(rp, c, v, m, seed=4)
+    a2, b2, V2, r2 = oracle.lanczos_emul(rp, c, v, m, "fp64", seed=4)
+    assert r1 == r2
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2) and np.array_equal(V1, V2)
+
+
+@pytest.mark.parametrize("mode,bits", [("bf16", 8), ("fp32", 24)])
+def test_lanczos_emul_stores_rounded_vectors(mode, bits):
+    # Every accepted Lanczos vector is a stored (rounded) vector scaled to
+    # unit length: V[:, i] * beta_{i+1} lies on the format's grid (up to the
+    # binary64 rounding of the division and product), and the rounding moves
+    # the coefficients by about the format's unit roundoff.
+    rp, c, v = synth.er(600, 9.0, seed=5)
+    m = 20
+    a, b, V, r = oracle.lanczos_emul(rp, c, v, m, mode, seed=5)
+    assert r == 0
+    for i in range(1, m):
+        w = V[:, i] * b[i]
+        g = np.array([oracle.round_bits(t, bits) for t in w])
+        assert np.all(np.abs(g - w) <= 8 * EPS * np.abs(w)), i
+    a64, b64, V64, _ = oracle.lanczos(rp, c, v, m, seed=5)
+    d = np.max(np.abs(a - a64)) / np.max(np.abs(a64))
+    u = 2.0 ** -bits
+    assert u / 100 < d < 100 * u, d
