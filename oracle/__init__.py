@@ -77,8 +77,18 @@ def _load():
         lib.orc_spmv_emul.argtypes = [i64, P, P, P, P, P, i32]
         lib.orc_lanczos_emul.restype = i32
         lib.orc_lanczos_emul.argtypes = [i64, P, P, P, i32, u64, i32, f64, i32, i32, i32, P, P, P]
+        lib.orc_start_vector.restype = None
+        lib.orc_start_vector.argtypes = [i64, u64, P]
+        lib.orc_set_progress.restype = None
+        lib.orc_set_progress.argtypes = [i32]
         _lib = lib
     return _lib
+
+
+def set_progress(on: bool) -> None:
+    """Print one line per Lanczos step on stderr (long runs); results are
+    unaffected."""
+    _load().orc_set_progress(1 if on else 0)
 
 
 def _p(a: np.ndarray):
@@ -99,6 +109,13 @@ def splitmix64(seed: int, r: int) -> int:
 
 def u01(seed: int, r: int) -> float:
     return float(_load().orc_u01(seed & (2 ** 64 - 1), r))
+
+
+def start_vector(n: int, seed: int = 0) -> np.ndarray:
+    """v_1 = u/||u|| with u_r = U01(SplitMix64(seed, r)), as lanczos() uses it."""
+    v = np.empty(n, dtype=np.float64)
+    _load().orc_start_vector(n, seed & (2 ** 64 - 1), _p(v))
+    return v
 
 
 def spmv(rowptr, col, val, x) -> np.ndarray:

@@ -38,8 +38,14 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Progress lines on stderr, one per Lanczos step (long runs on large
+ * matrices); no effect on any result. */
+static int orc_progress = 0;
+void orc_set_progress(int on) { orc_progress = on; }
 
 /* ------------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
@@ -93,6 +99,17 @@ static void mgs(int64_t n, const double *V, int cnt, double *w, int passes)
             double o = dot(n, vj, w);
             for (int64_t r = 0; r < n; ++r) w[r] -= o * vj[r];
         }
+}
+
+/*
+ * The start vector v_1 = u/||u||, u_r = U01(SplitMix64(seed, r)) (Algorithm 1
+ * takes an L2-normalised random vector), as orc_lanczos computes it.
+ */
+void orc_start_vector(int64_t n, uint64_t seed, double *v)
+{
+    for (int64_t r = 0; r < n; ++r) v[r] = orc_u01(seed, (uint64_t)r);
+    double s = nrm2(n, v);
+    for (int64_t r = 0; r < n; ++r) v[r] /= s;
 }
 
 /*
@@ -159,6 +176,7 @@ int orc_lanczos(int64_t n, const int64_t *rowptr, const int32_t *col,
         mgs(n, V, i, vn, passes);                               /* orthogonalise */
         double t = fabs(a) + bi;
         if (t > tnorm) tnorm = t;
+        if (orc_progress) { fprintf(stderr, "oracle: Lanczos step %d/%d\n", i, m); fflush(stderr); }
     }
     /* beta_{m+1} and v_{m+1} (residual estimate only). */
     double bl = nrm2(n, vn);
@@ -441,6 +459,7 @@ int orc_lanczos_emul(int64_t n, const int64_t *rowptr, const int32_t *col,
         mgs(n, V, i, vn, passes);
         double t = fabs(a) + bi;
         if (t > tnorm) tnorm = t;
+        if (orc_progress) { fprintf(stderr, "oracle (emulated): Lanczos step %d/%d\n", i, m); fflush(stderr); }
     }
     double *vl = V + (int64_t)m * n;
     double bl = store_unit(n, vn, vl, store_bits);

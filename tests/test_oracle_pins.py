@@ -64,6 +64,16 @@ def test_u01_is_top_53_bits():
     assert abs(u.mean() - 0.5) < 0.01 and abs(u.var() - 1 / 12) < 0.005
 
 
+def test_start_vector_is_normalised_u01_and_the_lanczos_v1():
+    n = 1000
+    u = np.array([(oracle.splitmix64(3, r) >> 11) / 2.0 ** 53 for r in range(n)])
+    v = oracle.start_vector(n, seed=3)
+    assert np.allclose(v, u / np.linalg.norm(u), rtol=1e-15, atol=0)
+    rp, c, val = synth.er(n, 6.0, seed=1)
+    _, _, V, _ = oracle.lanczos(rp, c, val, 3, seed=3)
+    assert np.array_equal(V[:, 0], v)
+
+
 # -------------------------------------------------------------- SpMV
 def test_spmv_matches_dense_product():
     A = random_sym(40, 1, density=0.3)
