@@ -57,6 +57,8 @@ typedef enum {
     LZ_ERR_NONFINITE = -7,          /* NaN or Inf appeared in beta */
     LZ_ERR_BREAKDOWN = -8,          /* a restart vector had no component
                                        outside the basis */
+    LZ_ERR_RESTART_BUDGET = -9,     /* stream-ordered call: more breakdowns
+                                       than lz_options.max_restarts */
     LZ_PENDING = 1                  /* serving: request not finished yet */
 } lz_status;
 
@@ -106,9 +108,27 @@ typedef struct lz_options {
                                 on `stream` (fills the t_* report fields) */
     int32_t reorder;         /* LZ_REORDER_*; default LZ_REORDER_AUTO */
     int32_t arith;           /* LZ_ARITH_*; default LZ_ARITH_MIXED */
+    int32_t max_restarts;    /* lanczos_topk_async: breakdowns the enqueued
+                                iterations can absorb, 0..LZ_MAX_RESTART_BUDGET;
+                                -1 (default) = m.  Ignored by the blocking
+                                calls, which enqueue more iterations after
+                                reading the step count back. */
 } lz_options;
 
-/* Results of one solve, filled on the host when the call returns. */
+#define LZ_MAX_RESTART_BUDGET 128
+
+/* Matrix layouts of the Lanczos-step SpMV (lz_report.spmv_layout). */
+#define LZ_LAYOUT_ROWS 0          /* caller's rows, entries in row order */
+#define LZ_LAYOUT_RELABELLED 1    /* hub-first rows, entries in row order */
+#define LZ_LAYOUT_TILE_SORTED 2   /* hub-first rows, each SpMV tile's entries
+                                     in column order (2^20 < n < 2^22) */
+#define LZ_LAYOUT_GROUP_SORTED 3  /* hub-first rows, entries of four
+                                     consecutive tiles in column order
+                                     (n <= 2^20) */
+#define LZ_LAYOUT_XCACHE 16       /* flag: head of x staged in LDS */
+
+/* Results of one solve: filled on the host when a blocking call returns, or
+ * written to device memory by the last kernel of lanczos_topk_async. */
 typedef struct lz_report {
     int32_t status;          /* lz_status of the solve */
     int32_t m_eff;           /* Lanczos steps taken (= m on success) */
@@ -138,7 +158,9 @@ typedef struct lz_report {
                                 a step (reorthogonalisation, launch gaps) */
     double t_finish_ms;      /* Jacobi, selection, Ritz vectors, report */
     int32_t reordered;       /* 1: the solve ran on the hub-first relabelling */
-    int32_t pad;
+    int32_t spmv_layout;     /* matrix layout the Lanczos-step SpMV read:
+                                LZ_LAYOUT_* plus LZ_LAYOUT_XCACHE when its
+                                workgroups kept the head of x in LDS */
     int64_t bytes_streamed;  /* lanczos_topk_host: host-to-device bytes of
                                 matrix entries (column indices and values)
                                 copied during the solve, the one copy of the
@@ -158,8 +180,12 @@ const char* lz_status_string(int status);
  *             lambda descending.
  *   out_vecs: device double[n*K], column-major (vector k at out_vecs+k*n),
  *             unit 2-norm, signed so its entry of largest modulus is positive.
- * Default options; the library allocates its workspace for the call.
- * Blocking: returns after the results are in out_vals/out_vecs.
+ * Default options; the library allocates its workspace for the call
+ * (stream-ordered, hipMallocAsync on `stream`).
+ * Blocking: reads nnz = rowptr[n] and, after the m iterations, the step count
+ * back from the device (more iterations follow breakdowns), and returns
+ * after the results are in out_vals/out_vecs.  lanczos_topk_async is the
+ * stream-ordered form.
  */
 int lanczos_topk(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val,
                  int64_t n, int32_t K, int32_t m, int32_t precision, void* stream,
@@ -172,12 +198,55 @@ size_t lanczos_topk_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m,
 /*
  * lanczos_topk with options and a report.  nnz must equal rowptr[n].
  * opt may be NULL (defaults); report may be NULL.  With a caller workspace
- * the call allocates nothing.  Blocking like lanczos_topk.
+ * the call allocates nothing; otherwise the workspace is allocated and freed
+ * stream-ordered on `stream`.  Blocking like lanczos_topk: it waits for the
+ * device after the m iterations (breakdown check, and the choice of SpMV
+ * variant once the row order is known) and at the end (report).
  */
 int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val,
                     int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision,
                     void* stream, double* out_vals, double* out_vecs,
                     const lz_options* opt, lz_report* report);
+
+/*
+ * Stream-ordered lanczos_topk_ex: every step is enqueued on `stream` and the
+ * call returns without waiting for the device, so it can be pipelined with
+ * other work or captured in a hipGraph (with a caller workspace: a
+ * stream-ordered allocation inside a capture becomes a graph node).
+ *   - The iterations are enqueued up front: m, plus opt->max_restarts more
+ *     (default m) that absorb breakdowns (each restart takes one iteration
+ *     that does not advance the step); those past the m-th step return at
+ *     once.  A solve needing more ends with status LZ_ERR_RESTART_BUDGET in
+ *     the report and leaves out_vals/out_vecs unwritten.
+ *   - The hub-first relabelling is decided on the device; where the choice
+ *     of SpMV variant depends on it, both variants are enqueued and the one
+ *     that does not apply returns at once.
+ *   - d_report: DEVICE pointer to an lz_report (or NULL), written by the last
+ *     kernel; timings are zero, and numerical outcomes (breakdown budget,
+ *     non-finite values, Jacobi limit, invalid column indices) appear only in
+ *     its status.
+ *   - Without opt->workspace the workspace is allocated with hipMallocAsync
+ *     and freed with hipFreeAsync on `stream`.
+ *   - opt->profile must be 0.
+ * Argument errors are returned before anything is enqueued.  Results equal
+ * those of lanczos_topk_ex with the same options bit for bit.
+ */
+int lanczos_topk_async(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val,
+                       int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision,
+                       void* stream, double* out_vals, double* out_vecs,
+                       const lz_options* opt, lz_report* d_report);
+
+/*
+ * Host utility for tests and callers that want to check the symmetry the
+ * solver assumes: returns 1 if the CSR matrix (host arrays; values in the
+ * storage type of `precision`; duplicate entries summed) equals its
+ * transpose, every pair of mirrored values agreeing within
+ * rtol * max(|a_ij|, |a_ji|); 0 if not, with *bad_row (if non-NULL) set to a
+ * row where it fails; a negative lz_status on invalid arguments (including
+ * column indices outside [0, n)).
+ */
+int lz_check_symmetric(const int64_t* rowptr, const int32_t* col, const void* val, int64_t n,
+                       int32_t precision, double rtol, int64_t* bad_row);
 
 /*
  * lanczos_topk_ex on a matrix whose entries stay in host memory, for matrices

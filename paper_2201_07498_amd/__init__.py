@@ -23,7 +23,7 @@ ARITH = {"mixed": 0, "fp32": 1}
 MAX_STEPS = 64
 STATUS = {0: "LZ_OK", -1: "LZ_ERR_INVALID_ARG", -2: "LZ_ERR_OUT_OF_MEMORY", -3: "LZ_ERR_HIP",
           -4: "LZ_ERR_WORKSPACE_TOO_SMALL", -5: "LZ_ERR_TOO_LARGE", -6: "LZ_ERR_NOT_CONVERGED",
-          -7: "LZ_ERR_NONFINITE", -8: "LZ_ERR_BREAKDOWN", 1: "LZ_PENDING"}
+          -7: "LZ_ERR_NONFINITE", -8: "LZ_ERR_BREAKDOWN", -9: "LZ_ERR_RESTART_BUDGET", 1: "LZ_PENDING"}
 
 
 class LanczosError(RuntimeError):
@@ -35,7 +35,8 @@ class LanczosError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("reorth", ctypes.c_int32), ("report", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("profile", ctypes.c_int32), ("reorder", ctypes.c_int32), ("arith", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("reorder", ctypes.c_int32), ("arith", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -47,7 +48,7 @@ class Report(ctypes.Structure):
                 ("beta", ctypes.c_double * (MAX_STEPS + 1)), ("theta", ctypes.c_double * MAX_STEPS),
                 ("t_setup_ms", ctypes.c_double), ("t_lanczos_ms", ctypes.c_double),
                 ("t_spmv_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double),
-                ("t_finish_ms", ctypes.c_double), ("reordered", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_finish_ms", ctypes.c_double), ("reordered", ctypes.c_int32), ("spmv_layout", ctypes.c_int32),
                 ("bytes_streamed", ctypes.c_int64)]
 
     def to_dict(self, K: int, m: int) -> dict:
@@ -59,7 +60,8 @@ class Report(ctypes.Structure):
                     beta=np.array(self.beta[:m + 1]), theta=np.array(self.theta[:m]),
                     t_setup_ms=self.t_setup_ms, t_lanczos_ms=self.t_lanczos_ms,
                     t_spmv_ms=self.t_spmv_ms, t_orth_ms=self.t_orth_ms, t_finish_ms=self.t_finish_ms,
-                    reordered=bool(self.reordered), bytes_streamed=int(self.bytes_streamed))
+                    reordered=bool(self.reordered), spmv_layout=int(self.spmv_layout),
+                    bytes_streamed=int(self.bytes_streamed))
 
 
 _lib = None
@@ -84,6 +86,10 @@ def lib() -> ctypes.CDLL:
         L.lanczos_topk_ex.restype = ctypes.c_int
         L.lanczos_topk_ex.argtypes = [P, P, P, i64, i64, i32, i32, i32, P, P, P,
                                       ctypes.POINTER(Options), ctypes.POINTER(Report)]
+        L.lanczos_topk_async.restype = ctypes.c_int
+        L.lanczos_topk_async.argtypes = [P, P, P, i64, i64, i32, i32, i32, P, P, P, ctypes.POINTER(Options), P]
+        L.lz_check_symmetric.restype = ctypes.c_int
+        L.lz_check_symmetric.argtypes = [P, P, P, i64, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
         L.lanczos_topk_host.restype = ctypes.c_int
         L.lanczos_topk_host.argtypes = [P, P, P, i64, i32, i32, i32, i64, i64, P, P, P,
                                         ctypes.POINTER(Options), ctypes.POINTER(Report)]
@@ -121,6 +127,23 @@ def _check_csr(rowptr, col, val, precision: int):
         raise TypeError(f"val must be a contiguous {want} device tensor")
 
 
+def _check_outputs(out, workspace, K: int, n: int, dev):
+    """The output and workspace tensors the library writes through raw
+    pointers: contiguous float64 device tensors of the right size, and a
+    device workspace, all on the matrix's device."""
+    import torch
+    if out is not None:
+        vals, vecs = out
+        for t, size, name in ((vals, K, "out[0]"), (vecs, K * n, "out[1]")):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.device == dev and t.dtype == torch.float64
+                    and t.is_contiguous() and t.numel() == size):
+                raise TypeError(f"{name} must be a contiguous float64 tensor of {size} elements on {dev}")
+    if workspace is not None:
+        if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda and workspace.device == dev
+                and workspace.is_contiguous()):
+            raise TypeError(f"workspace must be a contiguous tensor on {dev}")
+
+
 def workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
     return int(lib().lanczos_topk_workspace_size(n, nnz, K, m, _prec(precision)))
 
@@ -137,11 +160,23 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
     if nnz is None:
         nnz = col.numel()
     dev = rowptr.device
+    _check_outputs(out, workspace, K, n, dev)
     if out is None:
         vals = torch.empty(K, dtype=torch.float64, device=dev)
         vecs = torch.empty(K, n, dtype=torch.float64, device=dev)
     else:
         vals, vecs = out
+    opt = _options(seed, reorth, report, profile, reorder, arith, workspace)
+    rep = Report()
+    rc = lib().lanczos_topk_ex(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, nnz, K, m, p,
+                               _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(),
+                               ctypes.byref(opt), ctypes.byref(rep))
+    if rc != 0:
+        raise LanczosError(rc, "lanczos_topk_ex")
+    return vals, vecs.T, rep.to_dict(K, m)
+
+
+def _options(seed, reorth, report, profile, reorder, arith, workspace, max_restarts=-1) -> Options:
     opt = Options()
     lib().lz_options_init(ctypes.byref(opt))
     opt.seed = seed & (2 ** 64 - 1)
@@ -150,16 +185,69 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
     opt.profile = 1 if profile else 0
     opt.reorder = REORDER[reorder] if isinstance(reorder, str) else int(reorder)
     opt.arith = ARITH[arith] if isinstance(arith, str) else int(arith)
+    opt.max_restarts = int(max_restarts)
     if workspace is not None:
         opt.workspace = ctypes.c_void_p(workspace.data_ptr())
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
-    rep = Report()
-    rc = lib().lanczos_topk_ex(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, nnz, K, m, p,
-                               _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(),
-                               ctypes.byref(opt), ctypes.byref(rep))
+    return opt
+
+
+REPORT_BYTES = ctypes.sizeof(Report)
+
+
+def topk_async(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
+               report: bool = True, stream=None, workspace=None, nnz: int | None = None, out=None,
+               reorder="auto", arith="mixed", max_restarts: int = -1, d_report=None, _entry="lanczos_topk_async"):
+    """Stream-ordered Top-K (lanczos_topk_async): enqueues the solve on
+    `stream` and returns at once.  Returns (vals, vecs view, d_report), where
+    d_report is a uint8 device tensor holding the lz_report (read it with
+    report_from_device after the stream has finished)."""
+    import torch
+    p = _prec(precision)
+    _check_csr(rowptr, col, val, p)
+    n = rowptr.numel() - 1
+    if nnz is None:
+        nnz = col.numel()
+    dev = rowptr.device
+    _check_outputs(out, workspace, K, n, dev)
+    if out is None:
+        vals = torch.empty(K, dtype=torch.float64, device=dev)
+        vecs = torch.empty(K, n, dtype=torch.float64, device=dev)
+    else:
+        vals, vecs = out
+    if d_report is None:
+        d_report = torch.empty(REPORT_BYTES, dtype=torch.uint8, device=dev)
+    elif not (d_report.is_cuda and d_report.device == dev and d_report.dtype == torch.uint8
+              and d_report.is_contiguous() and d_report.numel() >= REPORT_BYTES):
+        raise TypeError(f"d_report must be a contiguous uint8 tensor of {REPORT_BYTES} bytes on {dev}")
+    opt = _options(seed, reorth, report, False, reorder, arith, workspace, max_restarts)
+    rc = getattr(lib(), _entry)(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, nnz, K, m, p,
+                                _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(), ctypes.byref(opt),
+                                ctypes.c_void_p(d_report.data_ptr()))
     if rc != 0:
-        raise LanczosError(rc, "lanczos_topk_ex")
-    return vals, vecs.T, rep.to_dict(K, m)
+        raise LanczosError(rc, _entry)
+    return vals, vecs.T, d_report
+
+
+def report_from_device(d_report, K: int, m: int) -> dict:
+    """Decodes an lz_report written to device memory (synchronises)."""
+    raw = bytes(d_report[:REPORT_BYTES].cpu().numpy().tobytes())
+    return Report.from_buffer_copy(raw).to_dict(K, m)
+
+
+def check_symmetric(rowptr, col, val, precision="fp64", rtol: float = 0.0):
+    """lz_check_symmetric on host numpy arrays (values in the storage type of
+    `precision`, bf16 as uint16 bits).  Returns (symmetric, bad_row)."""
+    p = _prec(precision)
+    rowptr = np.ascontiguousarray(rowptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, {LZ_FP64: np.float64, LZ_FP32: np.float32, LZ_BF16: np.uint16}[p])
+    bad = ctypes.c_int64(-1)
+    rc = lib().lz_check_symmetric(rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, rowptr.size - 1, p,
+                                  float(rtol), ctypes.byref(bad))
+    if rc < 0:
+        raise LanczosError(rc, "lz_check_symmetric")
+    return rc == 1, int(bad.value)
 
 
 def host_workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
@@ -180,22 +268,13 @@ def topk_host(rowptr, col, val, K: int, m: int, precision="fp64", slab_nnz: int 
         if t.is_cuda or t.dtype != dt or not t.is_contiguous():
             raise TypeError(f"{name} must be a contiguous {dt} host tensor")
     n = rowptr.numel() - 1
+    _check_outputs(out, workspace, K, n, torch.device(device))
     if out is None:
         vals = torch.empty(K, dtype=torch.float64, device=device)
         vecs = torch.empty(K, n, dtype=torch.float64, device=device)
     else:
         vals, vecs = out
-    opt = Options()
-    lib().lz_options_init(ctypes.byref(opt))
-    opt.seed = seed & (2 ** 64 - 1)
-    opt.reorth = REORTH[reorth] if isinstance(reorth, str) else int(reorth)
-    opt.report = 1 if report else 0
-    opt.profile = 1 if profile else 0
-    opt.reorder = REORDER["off"]
-    opt.arith = ARITH[arith] if isinstance(arith, str) else int(arith)
-    if workspace is not None:
-        opt.workspace = ctypes.c_void_p(workspace.data_ptr())
-        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    opt = _options(seed, reorth, report, profile, "off", arith, workspace)
     rep = Report()
     rc = lib().lanczos_topk_host(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, K, m, p, slab_nnz,
                                  resident_nnz, _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(),

@@ -1,12 +1,15 @@
 // C ABI of the Top-K Lanczos solver: argument checks, workspace planning and
 // the launch sequence of one solve.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "../../include/lanczos_topk.h"
 #include "lz_internal.h"
 #include "lz_ooc.h"
+#include "lz_solve.h"
 
 namespace lz {
 
@@ -128,6 +131,22 @@ static int check_options(const lz_options* opt, int32_t precision, lz_options* o
 
 namespace lz {
 
+int check_async(const int64_t* rowptr, const int32_t* col, const void* val, int64_t n, int64_t nnz, int32_t K,
+                int32_t m, int32_t precision, const double* out_vals, const double* out_vecs,
+                const lz_options* opt, lz_options* o, Plan* p, int* budget) {
+    int rc = check_common(rowptr, col, val, n, K, m, precision);
+    if (rc != LZ_OK) return rc;
+    if (!out_vals || !out_vecs || nnz < 0 || nnz >= (int64_t(1) << 40)) return LZ_ERR_INVALID_ARG;
+    rc = check_options(opt, precision, o);
+    if (rc != LZ_OK) return rc;
+    if (o->profile) return LZ_ERR_INVALID_ARG;
+    *budget = o->max_restarts < 0 ? m : o->max_restarts;
+    if (*budget > LZ_MAX_RESTART_BUDGET) return LZ_ERR_INVALID_ARG;
+    *p = make_plan(n, nnz, K, m, precision);
+    p->fff = o->arith == LZ_ARITH_FP32;
+    return LZ_OK;
+}
+
 // The launch sequence of one solve, shared by the device-resident and the
 // host-resident entry points (arguments already checked).  With hc, the
 // matrix entries stay in host memory and a.rowptr is a host array.
@@ -161,7 +180,7 @@ int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_val
     };
     {
         if (!ws) {
-            if (hipMalloc(&ws, p.bytes) != hipSuccess) return LZ_ERR_OUT_OF_MEMORY;
+            if (hipMallocAsync(&ws, p.bytes, s) != hipSuccess) return LZ_ERR_OUT_OF_MEMORY;
             owned = true;
         }
         const Bufs b = resolve(p, ws);
@@ -250,6 +269,7 @@ int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_val
             report->ritz_ortho_loss = hst->ritz_ortho_loss;
             report->mean_angle_deg = hst->mean_angle_deg;
             report->reordered = hst->reordered;
+            report->spmv_layout = (hst->reordered ? 1 + hst->packed : 0) | (p.xcache ? LZ_LAYOUT_XCACHE : 0);
             report->bytes_streamed = hc ? hc->ooc.streamed : 0;
             if (o.profile && launched > 0) {
                 float ms = 0.f;
@@ -275,10 +295,79 @@ done:
         if (hc->ooc.ks && ooc_end(hc->ooc, user) != hipSuccess && rc == LZ_OK) rc = LZ_ERR_HIP;
         ooc_release(hc->ooc);
     }
-    if (owned) (void)hipFree(ws);
+    if (owned) {
+        (void)hipFreeAsync(ws, s);
+        (void)hipStreamSynchronize(s);
+    }
     for (hipEvent_t e : iev) (void)hipEventDestroy(e);
     for (hipEvent_t e : pev)
         if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+// The results of a solve as an lz_report in device memory (stream-ordered
+// calls): status, step and restart counts, the Lanczos coefficients, Ritz
+// values, residuals and orthogonality metrics, as the blocking calls fill it
+// on the host; no timings.
+__global__ __launch_bounds__(BLOCK) void k_report(const State* st, lz_report* r, int xcache_if_relabelled) {
+    const int m = st->m, K = st->K, t = threadIdx.x;
+    if (t == 0) {
+        r->status = st->status;
+        r->m_eff = min(st->j, m);
+        r->restarts = st->restarts;
+        r->jacobi_sweeps = st->sweeps;
+        r->beta_last = st->beta[m];
+        r->ortho_loss = st->ortho_loss;
+        r->ritz_ortho_loss = st->ritz_ortho_loss;
+        r->mean_angle_deg = st->mean_angle_deg;
+        r->t_setup_ms = r->t_lanczos_ms = r->t_spmv_ms = r->t_orth_ms = r->t_finish_ms = 0.0;
+        r->reordered = st->reordered;
+        r->spmv_layout = st->reordered ? (1 + st->packed) | (xcache_if_relabelled ? LZ_LAYOUT_XCACHE : 0) : 0;
+        r->bytes_streamed = 0;
+    }
+    for (int i = t; i < LZ_MAX_STEPS; i += blockDim.x) {
+        r->resid[i] = i < K ? st->resid[i] : 0.0;
+        r->abs_resid[i] = i < K ? st->abs_resid[i] : 0.0;
+        r->alpha[i] = i < m ? st->alpha[i] : 0.0;
+        r->theta[i] = i < m ? st->theta[i] : 0.0;
+    }
+    for (int i = t; i <= LZ_MAX_STEPS; i += blockDim.x) r->beta[i] = i <= m ? st->beta[i] : 0.0;
+}
+
+hipError_t launch_report(const Plan&, const Bufs& b, void* d_report, int xcache_if_relabelled, hipStream_t s) {
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(BLOCK), 0, s, b.st, (lz_report*)d_report, xcache_if_relabelled);
+    return hipGetLastError();
+}
+
+// Stream-ordered solve: every step is enqueued on `s` and nothing waits for
+// the device.  The number of iterations is fixed when they are enqueued: m,
+// plus `budget` more that absorb breakdowns (each restart takes one
+// iteration that does not advance the step); iterations past the m-th step
+// return at once.  The row-order decision is made on the device, so both
+// SpMV variants that could apply are launched and each returns unless it
+// matches.  ws: the caller's workspace, or null to allocate one
+// stream-ordered (hipMallocAsync / hipFreeAsync on s).
+int run_solve_async(Plan p, Csr a, const lz_options& o, int budget, hipStream_t s, double* out_vals,
+                    double* out_vecs, void* d_report, void* ws) {
+    int rc = LZ_OK;
+    bool owned = false;
+    if (!ws) {
+        if (hipMallocAsync(&ws, p.bytes, s) != hipSuccess) return LZ_ERR_OUT_OF_MEMORY;
+        owned = true;
+    }
+    {
+        const Bufs b = resolve(p, ws);
+        p.strict_m = 1;
+        p.xcache = (o.reorder != LZ_REORDER_OFF && want_xcache(p, true)) ? XC_GATED : XC_OFF;
+        LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, o.reorder, s));
+        LZ_HIP(launch_init(p, b, s));
+        for (int t = 0; t < p.m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, o.reorth, s));
+        for (int t = 0; t < budget; ++t) LZ_HIP(launch_iteration(p, b, a, p.m, o.reorth, s));
+        LZ_HIP(launch_finish(p, b, a, out_vals, out_vecs, o.report, s));
+        if (d_report) LZ_HIP(launch_report(p, b, d_report, p.xcache != XC_OFF, s));
+    }
+done:
+    if (owned && hipFreeAsync(ws, s) != hipSuccess && rc == LZ_OK) rc = LZ_ERR_HIP;
     return rc;
 }
 
@@ -293,6 +382,7 @@ void lz_options_init(lz_options* opt) {
     opt->reorth = LZ_REORTH_TWICE;
     opt->report = 1;
     opt->reorder = LZ_REORDER_AUTO;
+    opt->max_restarts = -1;
 }
 
 const char* lz_status_string(int status) {
@@ -306,6 +396,7 @@ const char* lz_status_string(int status) {
         case LZ_ERR_NOT_CONVERGED: return "Jacobi did not converge";
         case LZ_ERR_NONFINITE: return "non-finite value in the Lanczos recurrence";
         case LZ_ERR_BREAKDOWN: return "restart vector lies in the Krylov basis";
+        case LZ_ERR_RESTART_BUDGET: return "more breakdowns than the stream-ordered call's restart budget";
         case LZ_PENDING: return "pending";
         default: return "unknown status";
     }
@@ -330,6 +421,89 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
     if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
     return run_solve(p, Csr{csr_rowptr, csr_col, csr_val, n, nnz}, o, (hipStream_t)stream, out_vals, out_vecs,
                      report, nullptr);
+}
+
+int lanczos_topk_async(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n,
+                       int64_t nnz, int32_t K, int32_t m, int32_t precision, void* stream, double* out_vals,
+                       double* out_vecs, const lz_options* opt, lz_report* d_report) {
+    lz_options o;
+    Plan p;
+    int budget = 0;
+    const int rc = check_async(csr_rowptr, csr_col, csr_val, n, nnz, K, m, precision, out_vals, out_vecs, opt, &o,
+                               &p, &budget);
+    if (rc != LZ_OK) return rc;
+    if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
+    return run_solve_async(p, Csr{csr_rowptr, csr_col, csr_val, n, nnz}, o, budget, (hipStream_t)stream, out_vals,
+                           out_vecs, d_report, o.workspace);
+}
+
+int lz_check_symmetric(const int64_t* rowptr, const int32_t* col, const void* val, int64_t n, int32_t precision,
+                       double rtol, int64_t* bad_row) {
+    if (!rowptr || n < 1 || precision < LZ_FP64 || precision > LZ_BF16 || !(rtol >= 0.0)) return LZ_ERR_INVALID_ARG;
+    const int64_t nnz = rowptr[n];
+    if (rowptr[0] != 0 || nnz < 0 || (nnz > 0 && (!col || !val))) return LZ_ERR_INVALID_ARG;
+    for (int64_t r = 0; r < n; ++r)
+        if (rowptr[r + 1] < rowptr[r]) return LZ_ERR_INVALID_ARG;
+    auto value = [&](int64_t e) -> double {
+        if (precision == LZ_FP64) return ((const double*)val)[e];
+        if (precision == LZ_FP32) return ((const float*)val)[e];
+        const uint32_t u = (uint32_t)((const uint16_t*)val)[e] << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    };
+    // Canonical form: each row's entries sorted by column, duplicates summed.
+    std::vector<int64_t> crp(n + 1, 0);
+    std::vector<int32_t> cc;
+    std::vector<double> cv;
+    cc.reserve((size_t)nnz);
+    cv.reserve((size_t)nnz);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t r = 0; r < n; ++r) {
+        row.clear();
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n) return LZ_ERR_INVALID_ARG;
+            row.emplace_back(col[e], value(e));
+        }
+        std::stable_sort(row.begin(), row.end(),
+                         [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                             return x.first < y.first;
+                         });
+        for (size_t i = 0; i < row.size();) {
+            double sum = 0.0;
+            size_t k = i;
+            for (; k < row.size() && row[k].first == row[i].first; ++k) sum += row[k].second;
+            cc.push_back(row[i].first);
+            cv.push_back(sum);
+            i = k;
+        }
+        crp[r + 1] = (int64_t)cc.size();
+    }
+    // Transpose by counting; rows of the transpose come out column-sorted.
+    std::vector<int64_t> trp(n + 1, 0);
+    for (int32_t c : cc) ++trp[c + 1];
+    for (int64_t r = 0; r < n; ++r) trp[r + 1] += trp[r];
+    std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
+    std::vector<int32_t> tc(cc.size());
+    std::vector<double> tv(cc.size());
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t e = crp[r]; e < crp[r + 1]; ++e) {
+            const int64_t at = fill[cc[e]]++;
+            tc[at] = (int32_t)r;
+            tv[at] = cv[e];
+        }
+    for (int64_t r = 0; r < n; ++r) {
+        bool ok = crp[r + 1] - crp[r] == trp[r + 1] - trp[r];
+        for (int64_t i = 0; ok && i < crp[r + 1] - crp[r]; ++i) {
+            const int64_t a = crp[r] + i, b = trp[r] + i;
+            ok = cc[a] == tc[b] && std::fabs(cv[a] - tv[b]) <= rtol * std::max(std::fabs(cv[a]), std::fabs(tv[b]));
+        }
+        if (!ok) {
+            if (bad_row) *bad_row = r;
+            return 0;
+        }
+    }
+    return 1;
 }
 
 size_t lanczos_topk_host_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision) {

@@ -184,12 +184,19 @@ __device__ void jacobi_load_tridiag(int m, const double* diag, const double* off
 
 // T from alpha_1..alpha_m and beta_2..beta_m, Jacobi, Top-K selection by
 // modulus (ties: larger value, then lower index); writes the eigenvalues.
-__global__ __launch_bounds__(JBLOCK) void k_jacobi_select(State* st, double* out_vals) {
+// With `strict` (stream-ordered calls, whose iteration budget is fixed when
+// they are enqueued), a solve that completed fewer than m steps because more
+// breakdowns occurred than the budget absorbs ends with LZ_ERR_RESTART_BUDGET.
+__global__ __launch_bounds__(JBLOCK) void k_jacobi_select(State* st, double* out_vals, int strict) {
     __shared__ double T[MMAX][MMAX + 1];
     __shared__ double S[MMAX][MMAX + 1];
     __shared__ double shd[JBLOCK / 64];
     __shared__ int rot_flag, sweeps;
     if (st->status != 0) return;
+    if (strict && st->j < st->m) {
+        if (threadIdx.x == 0) st->status = -9;     // LZ_ERR_RESTART_BUDGET
+        return;
+    }
     const int m = min(st->j, st->m);
     const int K = st->K;
     if (m < K) {
@@ -770,7 +777,7 @@ static hipError_t finish_p(const Plan& p, const Bufs& b, const Csr& a, double* o
                            int report, hipStream_t s) {
     using VT = typename Tr<P>::V;
     const VT* V = (const VT*)b.V;
-    hipLaunchKernelGGL(k_jacobi_select, dim3(1), dim3(JBLOCK), 0, s, b.st, out_vals);
+    hipLaunchKernelGGL(k_jacobi_select, dim3(1), dim3(JBLOCK), 0, s, b.st, out_vals, p.strict_m);
     switch (p.KB) {
 #define LZ_RITZ_CASE(KBV)                                                                                    \
     case KBV:                                                                                                \

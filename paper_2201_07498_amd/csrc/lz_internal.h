@@ -92,7 +92,10 @@ struct Plan {
     int64_t n = 0, nnz = 0, ld = 0;
     int32_t K = 0, m = 0, prec = 0, KB = 0;
     int32_t g_orth = 0, g_dense = 0, g_tile = 0;
-    int32_t xcache = 0;         // Lanczos-step SpMV keeps the head of x in LDS (set once the row order is known)
+    int32_t xcache = 0;         // Lanczos-step SpMV keeps the head of x in LDS: XC_OFF, XC_ON (set once the
+                                // row order is known) or XC_GATED (both variants launched; each returns
+                                // unless the device's row-order decision selects it)
+    int32_t strict_m = 0;       // the finish reports LZ_ERR_RESTART_BUDGET if fewer than m steps completed
     int32_t fff = 0;            // all-FP32 arithmetic (FP32 storage only): float instantiations
     int32_t g_slab = 0;         // grid of the per-slab launches of a host-resident matrix
     Ooc* ooc = nullptr;         // non-null: the matrix entries stay in host memory
@@ -102,6 +105,8 @@ struct Plan {
            off_col2 = 0, off_val2 = 0, off_perm = 0, off_iperm = 0, off_gm = 0;
     size_t bytes = 0;
 };
+
+enum XcacheChoice { XC_OFF = 0, XC_ON = 1, XC_GATED = 2 };
 
 inline size_t storage_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 inline size_t work_bytes(int prec) { return prec == 0 ? 8 : 4; }
@@ -180,6 +185,10 @@ inline bool want_xcache(const Plan& p, bool relabelled) {
 bool host_relabel_decision(const int64_t* rowptr_host, int64_t n, int64_t nnz, int reorder);
 hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
                          double* out_vecs, int report, hipStream_t s);
+// Copies the state into a device-resident lz_report (stream-ordered calls).
+// `xcache_if_relabelled`: the SpMV staged the head of x in LDS whenever the
+// device chose the hub-first order.
+hipError_t launch_report(const Plan& p, const Bufs& b, void* d_report, int xcache_if_relabelled, hipStream_t s);
 hipError_t launch_spmv_plain(const Plan& p, const Bufs& b, const Csr& a, const void* x, void* y,
                              hipStream_t s);
 hipError_t launch_jacobi_only(const double* alpha, const double* offdiag, int m, State* st,

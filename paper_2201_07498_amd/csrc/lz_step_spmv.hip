@@ -45,7 +45,8 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
                                                        uint32_t* tk, double* head, double* tail, double* part,
                                                        const int64_t* rp_a, const int32_t* col_a, const void* val_a,
                                                        const int64_t* rp_b, const int32_t* col_b, const void* val_b,
-                                                       int64_t tb, int64_t te, int slab, int nslab) {
+                                                       int64_t tb, int64_t te, int slab, int nslab,
+                                                       int gate) {
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
@@ -55,6 +56,10 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
     __shared__ int s_last;
     __shared__ VT xs[H];
     if (st->status != 0) return;
+    // Gated launch (the row order is decided on the device and the host does
+    // not wait for it): gate 1 runs only on the relabelled matrix, gate 0 only
+    // on the caller's, -1 always.
+    if (gate >= 0 && (st->reordered != 0) != (gate == 1)) return;
     const int j = st->j;
     if (j >= st->m) return;
     if (st->mode == MODE_RESTART) {
@@ -156,11 +161,13 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
             const int gx = (int)((g + 7) / 8 * 8);
             hipLaunchKernelGGL((k_spmv_step<P, XW, true, F>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
                                (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr,
-                               a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1);
-            return;
+                               a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1,
+                               p.xcache == XC_GATED ? 1 : -1);
+            if (p.xcache == XC_ON) return;
         }
     }
     {
+        const int gate = p.xcache == XC_GATED ? 0 : -1;
         // FP32/BF16 storage: one resident set of workgroups (5 wavefronts per
         // SIMD, 256 CUs), each walking its share, so no late workgroups form
         // a tail (R-MAT 20 FP32: 80.1 -> 76.7 us).  FP64 does better the
@@ -171,11 +178,13 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
         if (off32)
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(g), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1);
+                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1,
+                               gate);
         else
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, false>), dim3(g), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1);
+                               b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1,
+                               gate);
     }
 }
 
@@ -189,11 +198,11 @@ static hipError_t spmv_step_ooc(const Plan& p, const Bufs& b, const Csr& a, hipS
         if (off32)
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(p.g_slab), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns);
+                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns, -1);
         else
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, false>), dim3(p.g_slab), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns);
+                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns, -1);
     });
 }
 

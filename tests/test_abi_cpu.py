@@ -148,3 +148,82 @@ def test_host_workspace_excludes_the_relabelled_copy():
         assert 0 < host < dev
         assert dev - host >= nnz * (4 + vb) + 2 * n * 4 - 4 * 256
     assert lz.host_workspace_size(0, 1, 1, 1, "fp64") == 0
+
+
+def test_async_entry_point_rejects_bad_arguments_before_gpu_work():
+    L = lz.lib()
+    d = ctypes.c_void_p(16)
+    opt = lz.Options()
+    L.lz_options_init(ctypes.byref(opt))
+    assert opt.max_restarts == -1
+    assert L.lanczos_topk_async(d, d, d, 100, 500, 3, 2, 0, None, d, d, ctypes.byref(opt), None) == -1
+    assert L.lanczos_topk_async(d, d, d, 100, 500, 2, 4, 0, None, None, d, ctypes.byref(opt), None) == -1
+    opt.profile = 1                       # timings need host-side events
+    assert L.lanczos_topk_async(d, d, d, 100, 500, 2, 4, 0, None, d, d, ctypes.byref(opt), None) == -1
+    opt.profile = 0
+    opt.max_restarts = 129                # above LZ_MAX_RESTART_BUDGET
+    assert L.lanczos_topk_async(d, d, d, 100, 500, 2, 4, 0, None, d, d, ctypes.byref(opt), None) == -1
+    opt.max_restarts = 0
+    opt.workspace = d
+    opt.workspace_bytes = 1024            # far too small
+    assert L.lanczos_topk_async(d, d, d, 100, 500, 2, 4, 0, None, d, d, ctypes.byref(opt), None) == -4
+    assert L.lz_status_string(-9).startswith(b"more breakdowns")
+
+
+def test_report_struct_matches_the_header_layout():
+    # lz_report: 4 ints, beta_last, 2 x 64 residuals, 3 metrics, alpha[64],
+    # beta[65], theta[64], 5 timings, 2 ints, bytes_streamed.
+    assert lz.REPORT_BYTES == 4 * 4 + 8 + 2 * 64 * 8 + 3 * 8 + 64 * 8 + 65 * 8 + 64 * 8 + 5 * 8 + 2 * 4 + 8
+
+
+def test_check_symmetric():
+    import numpy as np
+    import synth
+    rp, c, v = synth.rmat(10, 8, seed=3)
+    for prec in ("fp64", "fp32", "bf16"):
+        assert lz.check_symmetric(rp, c, synth.to_storage(v, prec), prec) == (True, -1)
+    # One value changed: its row (or its mirror's) is reported.
+    w = v.copy()
+    w[rp[5]] += 0.25
+    ok, bad = lz.check_symmetric(rp, c, w, "fp64")
+    assert not ok and bad in (5, int(c[rp[5]]))
+    assert lz.check_symmetric(rp, c, w, "fp64", rtol=1.0)[0]
+    # Duplicates are summed: split one entry of an off-diagonal pair in two.
+    r = 7
+    e = int(rp[r])
+    rp2 = rp.copy()
+    rp2[r + 1:] += 1
+    c2 = np.insert(c, e + 1, c[e])
+    v2 = np.insert(v, e + 1, 0.5 * v[e])
+    v2[e] = 0.5 * v[e]
+    assert lz.check_symmetric(rp2, c2, v2, "fp64", rtol=1e-15)[0]
+    # A one-sided entry is caught; a column index outside [0, n) is an error.
+    p = synth.from_edges(4, [(0, 1)])
+    c3 = p[1].copy()
+    c3[0] = 2
+    assert not lz.check_symmetric(p[0], c3, p[2], "fp64")[0]
+    c3[0] = 9
+    with pytest.raises(lz.LanczosError):
+        lz.check_symmetric(p[0], c3, p[2], "fp64")
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    # The binding's Options and Report mirror lz_options and lz_report: same
+    # size and field offsets as a C compiler lays them out from the header.
+    import subprocess
+    src = tmp_path / "layout.c"
+    fields = {"lz_report": [f for f, _ in lz.Report._fields_], "lz_options": [f for f, _ in lz.Options._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-o", str(exe), str(src)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st, cls in (("lz_report", lz.Report), ("lz_options", lz.Options)):
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fields[st]:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
