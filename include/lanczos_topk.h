@@ -237,6 +237,31 @@ int lanczos_topk_async(const int64_t* csr_rowptr, const int32_t* csr_col, const 
                        const lz_options* opt, lz_report* d_report);
 
 /*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * lanczos_topk_async with its workspace in a fixed device array of the
+ * library instead of opt->workspace or a stream-ordered allocation.  Same
+ * arguments, kernels, results and report as lanczos_topk_async; the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *   - The array holds LZ_NOALLOC_SCRATCH_BYTES; a solve whose workspace
+ *     (lanczos_topk_workspace_size) is larger returns LZ_ERR_TOO_LARGE.
+ *   - opt->workspace must be NULL (else LZ_ERR_INVALID_ARG).
+ *   - Every GPU the library runs on holds its own copy of the array until
+ *     the process ends.  All calls on one GPU share it: calls that overlap
+ *     on one GPU (other streams, other threads) race; order them on one
+ *     stream.
+ *   - The array's device address is looked up once per device, on the
+ *     device's first call (that call returns LZ_ERR_HIP if it fails).
+ */
+#define LZ_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int lanczos_topk_noalloc(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val,
+                         int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision,
+                         void* stream, double* out_vals, double* out_vecs,
+                         const lz_options* opt, lz_report* d_report);
+/* LZ_NOALLOC_SCRATCH_BYTES, as the library was built. */
+size_t lanczos_topk_noalloc_max_bytes(void);
+
+/*
  * Host utility for tests and callers that want to check the symmetry the
  * solver assumes: returns 1 if the CSR matrix (host arrays; values in the
  * storage type of `precision`; duplicate entries summed) equals its

@@ -88,6 +88,10 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(Options), ctypes.POINTER(Report)]
         L.lanczos_topk_async.restype = ctypes.c_int
         L.lanczos_topk_async.argtypes = [P, P, P, i64, i64, i32, i32, i32, P, P, P, ctypes.POINTER(Options), P]
+        L.lanczos_topk_noalloc.restype = ctypes.c_int
+        L.lanczos_topk_noalloc.argtypes = [P, P, P, i64, i64, i32, i32, i32, P, P, P, ctypes.POINTER(Options), P]
+        L.lanczos_topk_noalloc_max_bytes.restype = ctypes.c_size_t
+        L.lanczos_topk_noalloc_max_bytes.argtypes = []
         L.lz_check_symmetric.restype = ctypes.c_int
         L.lz_check_symmetric.argtypes = [P, P, P, i64, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
         L.lanczos_topk_host.restype = ctypes.c_int
@@ -227,6 +231,19 @@ def topk_async(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0
     if rc != 0:
         raise LanczosError(rc, _entry)
     return vals, vecs.T, d_report
+
+
+def topk_noalloc(rowptr, col, val, K: int, m: int, precision="fp64", **kw):
+    """lanczos_topk_noalloc: topk_async with the library's fixed device
+    scratch array as the workspace (no device allocation; calls overlapping
+    on one device race).  Same arguments as topk_async except workspace."""
+    if kw.get("workspace") is not None:
+        raise TypeError("topk_noalloc takes no workspace")
+    return topk_async(rowptr, col, val, K, m, precision, _entry="lanczos_topk_noalloc", **kw)
+
+
+def noalloc_max_bytes() -> int:
+    return int(lib().lanczos_topk_noalloc_max_bytes())
 
 
 def report_from_device(d_report, K: int, m: int) -> dict:
