@@ -314,13 +314,6 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
                 for (int l = 0; l < nc; ++l) gc += sg[threadIdx.x][l] * sc[l];
                 c2 = sc[threadIdx.x] - gc;
             }
-            // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c) tells how much the
-            // first pass cancelled.
-            A sel[3] = {(int)threadIdx.x < nc ? c2 * c2 : A(0),
-                        (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : A(0),
-                        (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : A(0)};
-            for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
-            const A w1 = fmax(A(0), wn - A(2) * sel[1] + sel[2]);
             // c2 = c - G c corrects for G != I but not for the rounding of c
             // itself (about u_A ||w|| per coefficient, u_A the unit roundoff
             // of the dots), which stays in the new vector: its orthogonality
@@ -329,14 +322,31 @@ __global__ __launch_bounds__(OBLOCK) void k_orth_dot(State* st, const typename T
             // below ||A v_j||), the second coefficients are re-measured from
             // w' = w - V c, as classical Gram-Schmidt twice does
             // (k_orth_upd_dot), and the update then uses those.
+            // Only where the dots are no more precise than the storage (FP64
+            // storage, and the all-FP32 arithmetic): with FP32 or BF16
+            // storage and FP64 dots the loss stays below the storage rounding
+            // until ||w - V c|| is far under the breakdown threshold, so the
+            // iteration launcher leaves the re-measuring kernel out there.
             const A ua = sizeof(A) == 8 ? A(1.1102230246251565e-16) : A(5.9604644775390625e-08);
+            const bool can_remeasure = (double)ua >= st->u_s;
+            const bool selective = st->reorth == 3 && st->mode != MODE_RESTART;
+            // ||w - V c||^2 = ||w||^2 - 2 c.c + c.(G c) tells how much the
+            // first pass cancelled.
+            A sel[3] = {A(0), A(0), A(0)};
+            if (can_remeasure || selective) {
+                sel[0] = (int)threadIdx.x < nc ? c2 * c2 : A(0);
+                sel[1] = (int)threadIdx.x < nc ? sc[threadIdx.x] * sc[threadIdx.x] : A(0);
+                sel[2] = (int)threadIdx.x < nc ? sc[threadIdx.x] * (sc[threadIdx.x] - c2) : A(0);
+                for (int q = 0; q < 3; ++q) sel[q] = block_sum(sel[q], shd, OWAVES);
+            }
+            const A w1 = fmax(A(0), wn - A(2) * sel[1] + sel[2]);
             const A lim = ua / (A(100) * (A)st->u_s);
-            const bool remeasure = w1 < lim * lim * wn;
+            const bool remeasure = can_remeasure && w1 < lim * lim * wn;
             // Selective: skip the correction when it is below the rounding of
             // the stored vector, ||c2|| <= u_s ||w - V c||.  The two-pass mode
             // and restart vectors always apply it.
             bool corr = true;
-            if (st->reorth == 3 && st->mode != MODE_RESTART) {
+            if (selective) {
                 corr = sel[0] > (A)(st->u_s * st->u_s) * w1;
                 if (threadIdx.x == 0) st->wnorm2 = (double)w1;
             }
@@ -622,12 +632,16 @@ static hipError_t iteration_pa(const Plan& p, const Bufs& b, const Csr& a, int n
     if (es != hipSuccess) return es;
     if (ev) (void)hipEventRecord(ev[1], s);
     const int nb = nc_bucket(ncols);
+    // The two-pass modes re-measure their second coefficients only where the
+    // dots are no more precise than the storage (see k_orth_dot).
+    const bool remeasure_possible = P == 0 || sizeof(A) == 4;
 #define LZ_ORTH_CASE(NCV)                                                                                  \
     case NCV:                                                                                              \
         hipLaunchKernelGGL((k_orth_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w, p.ld,      \
                            b.part, b.part2, b.gm);                                                         \
-        hipLaunchKernelGGL((k_orth_upd_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w,        \
-                           p.ld, b.part, b.part2);                                                         \
+        if (reorth < 2 || remeasure_possible)                                                              \
+            hipLaunchKernelGGL((k_orth_upd_dot<P, NCV, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, w,    \
+                               p.ld, b.part, b.part2);                                                     \
         if (reorth >= 2)                                                                                   \
             hipLaunchKernelGGL((k_orth_upd_store<P, NCV, true, A>), dim3(p.g_orth), dim3(OBLOCK), 0, s, b.st, V, \
                                w, p.ld, b.part, b.part2, b.gm);                                            \
