@@ -113,6 +113,15 @@ def golden(name: str):
         return json.load(fh)
 
 
+LAYOUTS = {0: "caller's rows", 1: "hub-first rows", 2: "hub-first rows, tiles in column order",
+           3: "hub-first rows, tile groups in column order", 4: "hub-first rows, sweep blocks in column order"}
+
+
+def layout_name(code: int) -> str:
+    name = LAYOUTS.get(code & 15, str(code))
+    return name + (", x head in LDS" if code & 16 else "")
+
+
 def spmv_bytes(n: int, nnz: int, precision: str) -> int:
     """Algorithmic HBM bytes of one SpMV step: col + val per non-zero, the
     int64 row pointer, one read of x and of v_{j-1}, one write of w."""
@@ -664,7 +673,8 @@ def main():
         "ortho_loss": rep["ortho_loss"],
         "jacobi_sweeps": rep["jacobi_sweeps"],
         "relabelled": rep["reordered"],
-        "roofline": {"bound": "hbm", "kernel": "k_spmv (Lanczos step SpMV)",
+        "spmv_layout": layout_name(rep["spmv_layout"]),
+        "roofline": {"bound": "hbm", "kernel": f"k_spmv_step (Lanczos step SpMV; {layout_name(rep['spmv_layout'])})",
                      "achieved": R["spmv_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": R["spmv_gbps"] / HBM_PEAK_GBPS, "traffic": None,
                      "bytes_per_launch": R["spmv_bytes"]},

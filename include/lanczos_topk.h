@@ -113,7 +113,25 @@ typedef struct lz_options {
                                 -1 (default) = m.  Ignored by the blocking
                                 calls, which enqueue more iterations after
                                 reading the step count back. */
+    int32_t sweep;           /* LZ_SWEEP_*: sweep-block layout of a relabelled
+                                matrix; default LZ_SWEEP_AUTO */
 } lz_options;
+
+/* Sweep-block layout of the relabelled matrix for the Lanczos-step SpMV
+ * (lz_report.spmv_layout = LZ_LAYOUT_SWEEP): the rows are cut into blocks of
+ * at most 4096 rows and 2^18 entries (FP64; 2048 and 2^17 in FP32 and BF16),
+ * each block's entries are stored in
+ * column order with their row inside the block, and one wavefront walks a
+ * block gathering x in address order while it adds the products into per-row
+ * sums in LDS.  Costs a segmented sort at setup and 10 (FP32), 14 (FP64) or
+ * 8 (BF16) more bytes of workspace per entry, plus 8 bytes per entry of setup
+ * scratch; needs nnz < 2^32.  AUTO takes it for n >= 2^22 when x (n entries
+ * of the storage precision) is at least 64 MiB; ON whenever the matrix is
+ * relabelled; OFF never.  lanczos_topk_workspace_size() reports the AUTO
+ * size; lanczos_topk_workspace_size_opt() the size for given options. */
+#define LZ_SWEEP_AUTO (-1)
+#define LZ_SWEEP_OFF 0
+#define LZ_SWEEP_ON 1
 
 #define LZ_MAX_RESTART_BUDGET 128
 
@@ -125,6 +143,9 @@ typedef struct lz_options {
 #define LZ_LAYOUT_GROUP_SORTED 3  /* hub-first rows, entries of four
                                      consecutive tiles in column order
                                      (n <= 2^20) */
+#define LZ_LAYOUT_SWEEP 4         /* hub-first rows in sweep blocks, each
+                                     block's entries in column order
+                                     (LZ_SWEEP_*) */
 #define LZ_LAYOUT_XCACHE 16       /* flag: head of x staged in LDS */
 
 /* Results of one solve: filled on the host when a blocking call returns, or
@@ -191,9 +212,16 @@ int lanczos_topk(const int64_t* csr_rowptr, const int32_t* csr_col, const void* 
                  int64_t n, int32_t K, int32_t m, int32_t precision, void* stream,
                  double* out_vals, double* out_vecs);
 
-/* Device bytes of workspace a solve of this shape needs. */
+/* Device bytes of workspace a solve of this shape needs (default options). */
 size_t lanczos_topk_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m,
                                    int32_t precision);
+
+/* The same for the given options (opt NULL: defaults): the sweep-block copy
+ * (opt->sweep; none with opt->reorder = LZ_REORDER_OFF) changes it.  Returns 0
+ * for invalid arguments or options.  Host-only, no device calls beyond
+ * looking up the current device's properties. */
+size_t lanczos_topk_workspace_size_opt(int64_t n, int64_t nnz, int32_t K, int32_t m,
+                                       int32_t precision, const lz_options* opt);
 
 /*
  * lanczos_topk with options and a report.  nnz must equal rowptr[n].

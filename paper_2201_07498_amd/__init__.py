@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("reorth", ctypes.c_int32), ("report", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("profile", ctypes.c_int32), ("reorder", ctypes.c_int32), ("arith", ctypes.c_int32),
-                ("max_restarts", ctypes.c_int32)]
+                ("max_restarts", ctypes.c_int32), ("sweep", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.lanczos_topk.argtypes = [P, P, P, i64, i32, i32, i32, P, P, P]
         L.lanczos_topk_workspace_size.restype = ctypes.c_size_t
         L.lanczos_topk_workspace_size.argtypes = [i64, i64, i32, i32, i32]
+        L.lanczos_topk_workspace_size_opt.restype = ctypes.c_size_t
+        L.lanczos_topk_workspace_size_opt.argtypes = [i64, i64, i32, i32, i32, ctypes.POINTER(Options)]
         L.lanczos_topk_ex.restype = ctypes.c_int
         L.lanczos_topk_ex.argtypes = [P, P, P, i64, i64, i32, i32, i32, P, P, P,
                                       ctypes.POINTER(Options), ctypes.POINTER(Report)]
@@ -148,13 +150,18 @@ def _check_outputs(out, workspace, K: int, n: int, dev):
             raise TypeError(f"workspace must be a contiguous tensor on {dev}")
 
 
-def workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64") -> int:
-    return int(lib().lanczos_topk_workspace_size(n, nnz, K, m, _prec(precision)))
+def workspace_size(n: int, nnz: int, K: int, m: int, precision="fp64", sweep=None, reorder="auto") -> int:
+    """Workspace bytes of a device-resident solve (default options, or the
+    given sweep / reorder choice)."""
+    if sweep is None and reorder == "auto":
+        return int(lib().lanczos_topk_workspace_size(n, nnz, K, m, _prec(precision)))
+    opt = _options(0, "twice", True, False, reorder, "mixed", None, sweep=sweep)
+    return int(lib().lanczos_topk_workspace_size_opt(n, nnz, K, m, _prec(precision), ctypes.byref(opt)))
 
 
 def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
          report: bool = True, stream=None, workspace=None, nnz: int | None = None,
-         profile: bool = False, out=None, reorder="auto", arith="mixed"):
+         profile: bool = False, out=None, reorder="auto", arith="mixed", sweep=None):
     """Top-K eigenpairs.  Returns (vals[K], vecs[n, K] view of the column-major
     output, report dict)."""
     import torch
@@ -170,7 +177,7 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
         vecs = torch.empty(K, n, dtype=torch.float64, device=dev)
     else:
         vals, vecs = out
-    opt = _options(seed, reorth, report, profile, reorder, arith, workspace)
+    opt = _options(seed, reorth, report, profile, reorder, arith, workspace, sweep=sweep)
     rep = Report()
     rc = lib().lanczos_topk_ex(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, nnz, K, m, p,
                                _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(),
@@ -180,7 +187,10 @@ def topk(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reor
     return vals, vecs.T, rep.to_dict(K, m)
 
 
-def _options(seed, reorth, report, profile, reorder, arith, workspace, max_restarts=-1) -> Options:
+SWEEP = {None: -1, "auto": -1, False: 0, "off": 0, True: 1, "on": 1}
+
+
+def _options(seed, reorth, report, profile, reorder, arith, workspace, max_restarts=-1, sweep=None) -> Options:
     opt = Options()
     lib().lz_options_init(ctypes.byref(opt))
     opt.seed = seed & (2 ** 64 - 1)
@@ -190,6 +200,7 @@ def _options(seed, reorth, report, profile, reorder, arith, workspace, max_resta
     opt.reorder = REORDER[reorder] if isinstance(reorder, str) else int(reorder)
     opt.arith = ARITH[arith] if isinstance(arith, str) else int(arith)
     opt.max_restarts = int(max_restarts)
+    opt.sweep = SWEEP[sweep] if (sweep is None or isinstance(sweep, (str, bool))) else int(sweep)
     if workspace is not None:
         opt.workspace = ctypes.c_void_p(workspace.data_ptr())
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -201,7 +212,8 @@ REPORT_BYTES = ctypes.sizeof(Report)
 
 def topk_async(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0, reorth="twice",
                report: bool = True, stream=None, workspace=None, nnz: int | None = None, out=None,
-               reorder="auto", arith="mixed", max_restarts: int = -1, d_report=None, _entry="lanczos_topk_async"):
+               reorder="auto", arith="mixed", max_restarts: int = -1, d_report=None, sweep=None,
+               _entry="lanczos_topk_async"):
     """Stream-ordered Top-K (lanczos_topk_async): enqueues the solve on
     `stream` and returns at once.  Returns (vals, vecs view, d_report), where
     d_report is a uint8 device tensor holding the lz_report (read it with
@@ -224,7 +236,7 @@ def topk_async(rowptr, col, val, K: int, m: int, precision="fp64", seed: int = 0
     elif not (d_report.is_cuda and d_report.device == dev and d_report.dtype == torch.uint8
               and d_report.is_contiguous() and d_report.numel() >= REPORT_BYTES):
         raise TypeError(f"d_report must be a contiguous uint8 tensor of {REPORT_BYTES} bytes on {dev}")
-    opt = _options(seed, reorth, report, False, reorder, arith, workspace, max_restarts)
+    opt = _options(seed, reorth, report, False, reorder, arith, workspace, max_restarts, sweep)
     rc = getattr(lib(), _entry)(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), n, nnz, K, m, p,
                                 _stream_ptr(stream), vals.data_ptr(), vecs.data_ptr(), ctypes.byref(opt),
                                 ctypes.c_void_p(d_report.data_ptr()))

@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("lz_setup.hip", "lz_step_spmv.hip", "lz_kernels.hip", "lz_finish.hip", "lz_api.hip", "lz_ooc.hip", "lz_server.hip", "lz_noalloc.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("lz_setup.hip", "lz_step_spmv.hip", "lz_kernels.hip", "lz_finish.hip", "lz_api.hip", "lz_ooc.hip", "lz_server.hip", "lz_noalloc.hip", "lz_sweep.hip")]
 LIB = os.path.join(HERE, "liblanczos_topk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

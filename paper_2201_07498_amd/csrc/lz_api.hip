@@ -21,7 +21,7 @@ static int pow2_ge(int k) {
     return v;
 }
 
-Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool relabel) {
+Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool relabel, int sweep) {
     Plan p;
     p.n = n;
     p.nnz = nnz;
@@ -69,6 +69,26 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool 
     p.off_perm = take(relabel ? (size_t)n * 4 : 0);
     p.off_iperm = take(relabel ? (size_t)n * 4 : 0);
     p.off_gm = take((size_t)NCMAX * NCMAX * 8);
+    p.sweep = relabel && sweep_applies(n, nnz, prec, sweep);
+    if (p.sweep) {
+        p.sw_items = (int64_t)SW_W * sweep_rows(prec);
+        p.sw_nb = ceil_div(nnz + SW_W * n, p.sw_items);
+        // Sort on the line of x an entry gathers (128 bytes), up to the
+        // highest column bit.
+        int bits = 0;
+        while (bits < 31 && (int64_t(1) << bits) < n) ++bits;
+        const int line = vb == 8 ? 4 : (vb == 4 ? 5 : 6);
+        p.sw_bit1 = bits;
+        p.sw_bit0 = line < bits ? line : 0;
+        p.sw_sort_bytes = sweep_sort_bytes(nnz, p.sw_nb);
+        p.off_swob = take((size_t)(p.sw_nb + 1) * 4);
+        p.off_swe = take((size_t)(p.sw_nb + 1) * 8);
+        p.off_swcol = take((size_t)nnz * 4);
+        p.off_swrl = take((size_t)nnz * 2);
+        p.off_swval = take((size_t)nnz * vb);
+        p.off_swsrc = take((size_t)nnz * 4);
+        p.off_swtmp = take(p.sw_sort_bytes);
+    }
     p.bytes = o;
     return p;
 }
@@ -96,6 +116,13 @@ Bufs resolve(const Plan& p, void* base) {
     b.perm = (int32_t*)(c + p.off_perm);
     b.iperm = (int32_t*)(c + p.off_iperm);
     b.gm = (double*)(c + p.off_gm);
+    b.swob = p.sweep ? (int32_t*)(c + p.off_swob) : nullptr;
+    b.swe = p.sweep ? (int64_t*)(c + p.off_swe) : nullptr;
+    b.swcol = p.sweep ? (int32_t*)(c + p.off_swcol) : nullptr;
+    b.swrl = p.sweep ? (uint16_t*)(c + p.off_swrl) : nullptr;
+    b.swval = p.sweep ? c + p.off_swval : nullptr;
+    b.swsrc = p.sweep ? (uint32_t*)(c + p.off_swsrc) : nullptr;
+    b.swtmp = p.sweep ? c + p.off_swtmp : nullptr;
     return b;
 }
 
@@ -126,7 +153,16 @@ static int check_options(const lz_options* opt, int32_t precision, lz_options* o
     if (o.reorder < LZ_REORDER_OFF || o.reorder > LZ_REORDER_AUTO) return LZ_ERR_INVALID_ARG;
     if (o.arith < LZ_ARITH_MIXED || o.arith > LZ_ARITH_FP32) return LZ_ERR_INVALID_ARG;
     if (o.arith == LZ_ARITH_FP32 && precision != LZ_FP32) return LZ_ERR_INVALID_ARG;
+    if (o.sweep < LZ_SWEEP_AUTO || o.sweep > LZ_SWEEP_ON) return LZ_ERR_INVALID_ARG;
     return LZ_OK;
+}
+
+// The plan of a device-resident solve with these options (the sweep-block
+// copy only where the matrix may be relabelled).
+static Plan plan_for(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision, const lz_options& o) {
+    Plan p = make_plan(n, nnz, K, m, precision, true, o.reorder == LZ_REORDER_OFF ? LZ_SWEEP_OFF : o.sweep);
+    p.fff = o.arith == LZ_ARITH_FP32;
+    return p;
 }
 
 namespace lz {
@@ -142,8 +178,7 @@ int check_async(const int64_t* rowptr, const int32_t* col, const void* val, int6
     if (o->profile) return LZ_ERR_INVALID_ARG;
     *budget = o->max_restarts < 0 ? m : o->max_restarts;
     if (*budget > LZ_MAX_RESTART_BUDGET) return LZ_ERR_INVALID_ARG;
-    *p = make_plan(n, nnz, K, m, precision);
-    p->fff = o->arith == LZ_ARITH_FP32;
+    *p = plan_for(n, nnz, K, m, precision, *o);
     return LZ_OK;
 }
 
@@ -217,7 +252,7 @@ int run_solve(Plan p, Csr a, const lz_options& o, hipStream_t s, double* out_val
             LZ_HIP(pe);
             p.ooc = &hc->ooc;
         }
-        if (!hc && o.reorder != LZ_REORDER_OFF && want_xcache(p, true)) {
+        if (!hc && o.reorder != LZ_REORDER_OFF && !p.sweep && want_xcache(p, true)) {
             // The SpMV variant depends on the row order the device chose.
             LZ_HIP(hipMemcpyAsync(hst, b.st, offsetof(State, maxdeg), hipMemcpyDeviceToHost, s));
             LZ_HIP(hipStreamSynchronize(s));
@@ -358,7 +393,7 @@ int run_solve_async(Plan p, Csr a, const lz_options& o, int budget, hipStream_t 
     {
         const Bufs b = resolve(p, ws);
         p.strict_m = 1;
-        p.xcache = (o.reorder != LZ_REORDER_OFF && want_xcache(p, true)) ? XC_GATED : XC_OFF;
+        p.xcache = (o.reorder != LZ_REORDER_OFF && !p.sweep && want_xcache(p, true)) ? XC_GATED : XC_OFF;
         LZ_HIP(launch_setup(p, b, a, o.seed, o.reorth, o.reorder, s));
         LZ_HIP(launch_init(p, b, s));
         for (int t = 0; t < p.m; ++t) LZ_HIP(launch_iteration(p, b, a, t + 1, o.reorth, s));
@@ -383,6 +418,7 @@ void lz_options_init(lz_options* opt) {
     opt->report = 1;
     opt->reorder = LZ_REORDER_AUTO;
     opt->max_restarts = -1;
+    opt->sweep = LZ_SWEEP_AUTO;
 }
 
 const char* lz_status_string(int status) {
@@ -407,6 +443,14 @@ size_t lanczos_topk_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t m,
     return make_plan(n, nnz, K, m, precision).bytes;
 }
 
+size_t lanczos_topk_workspace_size_opt(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t precision,
+                                       const lz_options* opt) {
+    if (n < 1 || nnz < 0 || K < 1 || m < K || m > LZ_MAX_STEPS || precision < 0 || precision > 2) return 0;
+    lz_options o;
+    if (check_options(opt, precision, &o) != LZ_OK) return 0;
+    return plan_for(n, nnz, K, m, precision, o).bytes;
+}
+
 int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const void* csr_val, int64_t n, int64_t nnz,
                     int32_t K, int32_t m, int32_t precision, void* stream, double* out_vals, double* out_vecs,
                     const lz_options* opt, lz_report* report) {
@@ -416,8 +460,7 @@ int lanczos_topk_ex(const int64_t* csr_rowptr, const int32_t* csr_col, const voi
     lz_options o;
     rc = check_options(opt, precision, &o);
     if (rc != LZ_OK) return rc;
-    Plan p = make_plan(n, nnz, K, m, precision);
-    p.fff = o.arith == LZ_ARITH_FP32;
+    Plan p = plan_for(n, nnz, K, m, precision, o);
     if (o.workspace && o.workspace_bytes < p.bytes) return LZ_ERR_WORKSPACE_TOO_SMALL;
     return run_solve(p, Csr{csr_rowptr, csr_col, csr_val, n, nnz}, o, (hipStream_t)stream, out_vals, out_vecs,
                      report, nullptr);

@@ -25,7 +25,10 @@ constexpr int GRAM_PARTS = 1024; // Gram kernel grid cap (per-workgroup 64x64 pa
 // word holds (col << PACK_SLOTBITS) | (the entry's position in the tile's row
 // order).  PACK_GROUP (n <= 2^20): the same over groups of GROUP_TILES
 // consecutive tiles, with GROUP_SLOTBITS-bit positions in the group.
-enum Packing { PACK_NONE = 0, PACK_TILE = 1, PACK_GROUP = 2 };
+// PACK_SWEEP (large matrices, opt-in below a size threshold): the rows are
+// cut into sweep blocks and each block's entries are stored in column order
+// with their row inside the block in a separate array (see below).
+enum Packing { PACK_NONE = 0, PACK_TILE = 1, PACK_GROUP = 2, PACK_SWEEP = 3 };
 constexpr int PACK_SLOTBITS = 10;   // TILE = 2^10 positions
 constexpr int PACK_COLBITS = 22;
 constexpr uint32_t PACK_SLOTMASK = (1u << PACK_SLOTBITS) - 1u;
@@ -33,6 +36,27 @@ constexpr int GROUP_TILES = 4;
 constexpr int GROUP_SLOTBITS = 12;  // GROUP_TILES * TILE = 2^12 positions
 constexpr int GROUP_COLBITS = 20;
 constexpr uint32_t GROUP_SLOTMASK = (1u << GROUP_SLOTBITS) - 1u;
+// Sweep blocks: the relabelled matrix walked as one sequence of items, the
+// entries of row 0, SW_W items for the end of row 0, the entries of row 1,
+// and so on (entry e of row r is item e + SW_W * r); with R rows per block
+// (sweep_rows: 4096 in FP64, 2048 in FP32 and BF16) block b is items
+// [b * SW_W * R, (b+1) * SW_W * R) and owns the rows whose end starts in it,
+// so a block holds at most SW_W * R entries and R owned rows.  Its
+// entries are stored sorted by column (by the 128-byte line of x they
+// gather, ties in row order), each with its row relative to the block's
+// first owned row; the row continuing past the block, if any, comes right
+// after the owned ones (so at most R + 1 rows).
+constexpr int SW_W = 64;
+constexpr int SW_ROWS_MAX = 4096;
+constexpr int sweep_rows(int prec) { return prec == 0 ? 4096 : 2048; }
+// Automatic choice: relabelled matrices whose x takes at least 64 MiB.
+// Measured on MI355X, whole solve (K = 8, m = 32) of R-MAT with edge factor
+// 16, tiles -> sweep blocks: scale 24 FP32 149 -> 135 ms, FP64 196 -> 180,
+// BF16 (x 32 MiB) 118 -> 120; scale 25 FP32 337 -> 280, BF16 249 -> 242,
+// FP64 444 -> 366; scale 26 FP32 769 -> 634, BF16 578 -> 520.  At scale 23
+// in FP32 (x 32 MiB) the step SpMV was slower in sweep blocks.
+constexpr int64_t SWEEP_AUTO_MIN_N = int64_t(1) << 22;
+constexpr uint64_t SWEEP_AUTO_MIN_X_BYTES = uint64_t(1) << 26;
 
 enum Mode { MODE_NORMAL = 0, MODE_RESTART = 1 };
 
@@ -99,11 +123,17 @@ struct Plan {
     int32_t strict_m = 0;       // the finish reports LZ_ERR_RESTART_BUDGET if fewer than m steps completed
     int32_t fff = 0;            // all-FP32 arithmetic (FP32 storage only): float instantiations
     int32_t g_slab = 0;         // grid of the per-slab launches of a host-resident matrix
+    int32_t sweep = 0;          // reserve and build the sweep-block copy if the matrix is relabelled
+    int32_t sw_bit0 = 0, sw_bit1 = 0;   // column bits the sweep blocks are sorted on
+    int64_t sw_nb = 0;          // sweep blocks
+    int64_t sw_items = 0;       // items per sweep block (SW_W * sweep_rows)
+    size_t sw_sort_bytes = 0;   // scratch of the segmented sort
     Ooc* ooc = nullptr;         // non-null: the matrix entries stay in host memory
     int64_t n_tiles = 0;
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
            off_Y = 0, off_Z = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0, off_tail = 0, off_rp2 = 0,
-           off_col2 = 0, off_val2 = 0, off_perm = 0, off_iperm = 0, off_gm = 0;
+           off_col2 = 0, off_val2 = 0, off_perm = 0, off_iperm = 0, off_gm = 0, off_swob = 0, off_swe = 0,
+           off_swcol = 0, off_swrl = 0, off_swval = 0, off_swsrc = 0, off_swtmp = 0;
     size_t bytes = 0;
 };
 
@@ -120,8 +150,17 @@ inline double work_roundoff(int prec) { return prec == 0 ? 1.1102230246251565e-1
 
 // `relabel`: reserve the hub-first relabelled copy of the matrix (without it
 // the row-pointer slot still holds n + 1 entries, the device copy of the row
-// pointers of a host-resident matrix).
-Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool relabel = true);
+// pointers of a host-resident matrix).  `sweep`: LZ_SWEEP_* request; the
+// sweep-block copy is reserved when it applies (sweep_applies).
+Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool relabel = true,
+               int sweep = -1);
+// Whether a relabelled matrix of this size gets the sweep-block copy:
+// request 1 always (if the sort's 32-bit sizes reach), 0 never, -1 (auto)
+// where its SpMV measured faster than the tile layouts.
+bool sweep_applies(int64_t n, int64_t nnz, int prec, int request);
+// Scratch bytes of the segmented sort of nnz entries in nb blocks (its own
+// size query).
+size_t sweep_sort_bytes(int64_t nnz, int64_t nb);
 
 // Device pointers of a solve, resolved from a plan and a workspace base.
 struct Bufs {
@@ -145,6 +184,16 @@ struct Bufs {
     int32_t* perm;
     int32_t* iperm;
     double* gm;        // Gram matrix of the unit stored basis, NCMAX x NCMAX
+    // Sweep-block copy (Plan.sweep): first owned row and first entry of
+    // every block (nb + 1), the entries' columns, rows within the block and
+    // values in column order; the sort's source positions and scratch.
+    int32_t* swob;
+    int64_t* swe;
+    int32_t* swcol;
+    uint16_t* swrl;
+    void* swval;
+    uint32_t* swsrc;
+    void* swtmp;
 };
 Bufs resolve(const Plan& p, void* base);
 
@@ -184,6 +233,9 @@ inline bool want_xcache(const Plan& p, bool relabelled) {
 // The relabelling decision of the setup kernels, for callers that hold the
 // row pointer on the host (same integer test as on the device).
 bool host_relabel_decision(const int64_t* rowptr_host, int64_t n, int64_t nnz, int reorder);
+// Builds the sweep-block copy from the relabelled matrix (kernels return
+// unless the device chose PACK_SWEEP; the sort then sees empty blocks).
+hipError_t launch_sweep_setup(const Plan& p, const Bufs& b, hipStream_t s);
 hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
                          double* out_vecs, int report, hipStream_t s);
 // Copies the state into a device-resident lz_report (stream-ordered calls).

@@ -390,7 +390,7 @@ int lz_server_submit(lz_server* srv, const lz_request* req, uint64_t* ticket) {
     q->plan = make_plan(req->n, req->nnz, req->K, req->m, req->precision);
     // The SpMV variant is fixed when the graph is captured: take the device's
     // relabelling decision on the host, from the caller's row pointer.
-    if (want_xcache(q->plan, true))
+    if (!q->plan.sweep && want_xcache(q->plan, true))
         q->plan.xcache = want_xcache(q->plan, host_relabel_decision(req->rowptr, req->n, req->nnz, LZ_REORDER_AUTO));
     q->lay = layout_of(q->plan);
     std::lock_guard<std::mutex> lk(s->mu);

@@ -103,7 +103,7 @@ void launch_validate_cols(State* st, const int32_t* col, int64_t e0, int64_t e1,
 // Chooses the matrix of the solve and publishes its pointers in the state.
 __global__ void k_reorder_decide(State* st, const int64_t* rp, const int32_t* col, const void* val, int64_t n,
                                  int64_t nnz, int64_t* rp2, int32_t* col2, void* val2, int32_t* perm,
-                                 int32_t* iperm) {
+                                 int32_t* iperm, int sweep) {
     if (threadIdx.x != 0) return;
     const int opt = st->reorder;
     bool use = false;
@@ -114,6 +114,7 @@ __global__ void k_reorder_decide(State* st, const int64_t* rp, const int32_t* co
     }
     st->reordered = use ? 1 : 0;
     st->packed = !use ? PACK_NONE
+                 : sweep ? PACK_SWEEP
                  : n <= (int64_t(1) << GROUP_COLBITS) ? PACK_GROUP
                  : n < (int64_t(1) << PACK_COLBITS) ? PACK_TILE : PACK_NONE;
     st->crp = use ? rp2 : rp;
@@ -565,7 +566,7 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
     const int gv = (int)std::min<int64_t>((std::max(n, nnz) + BLOCK - 1) / BLOCK, 1024);
     hipLaunchKernelGGL(k_validate, dim3(gv), dim3(BLOCK), 0, s, b.st, a.rowptr, a.col, n, nnz);
     hipLaunchKernelGGL(k_reorder_decide, dim3(1), dim3(64), 0, s, b.st, a.rowptr, a.col, a.val, n, nnz, b.rp2,
-                       b.col2, b.val2, b.perm, b.iperm);
+                       b.col2, b.val2, b.perm, b.iperm, p.sweep);
     const int32_t* gate = &b.st->reordered;
     if (reorder != LZ_REORDER_OFF) {
         const int64_t nch = (n + CHR - 1) / CHR;
@@ -616,6 +617,8 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
                                    (uint16_t*)b.val2);
                 break;
         }
+        const hipError_t e = launch_sweep_setup(p, b, s);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

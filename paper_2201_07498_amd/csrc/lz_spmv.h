@@ -400,4 +400,120 @@ __device__ __forceinline__ void spmv_groups(const int64_t* __restrict__ rp, cons
     }
 }
 
+// ------------------------------------------------------------ sweep blocks
+// The sweep-block copy of the relabelled matrix (layout in lz_internal.h).
+struct SweepArgs {
+    const int32_t* ob;    // first owned row of every block (nb + 1)
+    const int64_t* e;     // first entry of every block (nb + 1)
+    const int32_t* col;   // columns, column order within each block
+    const uint16_t* rl;   // row of each entry relative to ob[b]
+    const void* val;
+    int64_t nb;
+};
+constexpr int SW_U = 8;        // entries per lane in flight
+// Rows per block, wavefronts per workgroup (their row sums fill the LDS, so
+// one workgroup per CU) and grid, per storage precision.  Measured on
+// MI355X, R-MAT scale 26 step SpMV (rows/wavefronts/grid): FP64 4096/4/1024
+// 14.3 ms, 4096/4/512 15.0, 2048/8/512 16.5; FP32 2048/8/512 12.4 ms,
+// 4096/4/1024 12.6, 4096/4/512 13.0, 2048/4/512 13.2; BF16 2048/8/512
+// 9.7 ms, 2048/4/512 10.3, 4096/4/1024 11.7, 4096/4/512 12.3.
+template <int P> struct SweepShape { static constexpr int ROWS = 2048, WAVES = 8, GRID = 512; };
+template <> struct SweepShape<0> { static constexpr int ROWS = 4096, WAVES = 4, GRID = 1024; };
+static_assert(SweepShape<0>::ROWS == sweep_rows(0) && SweepShape<1>::ROWS == sweep_rows(1) &&
+                  SweepShape<2>::ROWS == sweep_rows(2) && SweepShape<0>::ROWS <= SW_ROWS_MAX,
+              "sweep block rows");
+
+// Wavefront per sweep block, blocks dealt round-robin over all wavefronts
+// of the grid.  A block zeroes its row sums in LDS (owned rows, then the row
+// continuing past it), walks its entries in stored (column) order, 64 * SW_U
+// at a time, adding each product into its row's sum with an LDS atomic, and
+// then hands every owned row to the epilogue, one lane per row.  The sums
+// are binary64 in every storage mode: a hub row can put all of a block's
+// 2^18 products into one sum, and a binary32 chain that long loses about
+// sqrt(2^18) units of its last place (on a matrix with such rows, binary32
+// sums put the FP32-storage Ritz values 1.6e-6 from the FP64 ones); the
+// products of FP32 and BF16 values are exact in binary64.  Split rows
+// work as for tiles: the block that owns a row whose entries began in
+// earlier blocks publishes a head piece, every block a row continues past
+// publishes a tail piece, and the last piece to arrive on the owner's ticket
+// adds them in block order.  Each wavefront has its own sums and adds into
+// them in a fixed instruction order, so the result does not depend on timing.
+template <class VT, int NW, int ROWS, class Pre, class Row, class Piece, class Fin>
+__device__ __forceinline__ void spmv_sweep(const SweepArgs& sw, const int64_t* __restrict__ rp,
+                                           const VT* __restrict__ x, int64_t n, uint32_t* tk, double* head,
+                                           double* tail, Pre&& pre, Row&& row, Piece&& piece, Fin&& fin) {
+    constexpr int64_t ITEMS = (int64_t)SW_W * ROWS;
+    __shared__ double ys_all[NW][ROWS + 1];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double* ys = ys_all[w];
+    const int32_t* __restrict__ col = sw.col;
+    const uint16_t* __restrict__ rlv = sw.rl;
+    const VT* __restrict__ val = (const VT*)sw.val;
+    const int64_t nw = (int64_t)gridDim.x * NW;
+    for (int64_t b = (int64_t)blockIdx.x * NW + w; b < sw.nb; b += nw) {
+        const int64_t r0 = sw.ob[b], r1 = sw.ob[b + 1];
+        const int64_t e0 = sw.e[b], e1 = sw.e[b + 1];
+        const int nown = (int)(r1 - r0);
+        for (int i = lane; i <= nown; i += 64) ys[i] = 0.0;
+        wave_sync();
+        for (int64_t base = e0; base < e1; base += 64 * SW_U) {
+            int c[SW_U], r[SW_U];
+            VT v[SW_U];
+#pragma unroll
+            for (int q = 0; q < SW_U; ++q) {
+                const int64_t k = min(base + q * 64 + lane, e1 - 1);
+                c[q] = __builtin_nontemporal_load(col + k);
+                r[q] = (int)__builtin_nontemporal_load(rlv + k);
+                v[q] = __builtin_nontemporal_load(val + k);
+            }
+#pragma unroll
+            for (int q = 0; q < SW_U; ++q) {
+                const bool warm = (uint32_t)c[q] < GATHER_WARM_BYTES / (uint32_t)sizeof(VT);
+                const VT xv = warm ? x[c[q]] : __builtin_nontemporal_load(x + c[q]);
+                if (base + q * 64 + lane < e1)
+                    __hip_atomic_fetch_add(ys + min(r[q], nown), to_a(v[q], 0.0) * to_a(xv, 0.0),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+        }
+        wave_sync();
+        const bool split_head = nown > 0 && rp[r0] < e0;
+        double head_s = 0.0;
+        for (int i = lane; i < nown; i += 64) {
+            const int64_t rr = r0 + i;
+            const double s = ys[i];
+            if (i == 0 && split_head) {
+                head_s = s;
+                piece(rr, s);
+            } else {
+                row(rr, s, pre(rr));
+            }
+        }
+        if (split_head) {
+            if (lane == 0) st_dev(&head[b], head_s);
+            const int64_t t1 = (rp[r0] + SW_W * r0) / ITEMS;
+            if (last_wave(&tk[b], (uint32_t)(b - t1 + 1))) {
+                const double tot = split_total(head, tail, t1, b, lane);
+                if (lane == 0) fin(r0, tot);
+            }
+        }
+        if (r1 < n) {
+            const int64_t rb = rp[r1];
+            if (rb < e1) {
+                const double s = ys[nown];
+                if (lane == 0) {
+                    piece(r1, s);
+                    st_dev(&tail[b], s);
+                }
+                const int64_t t1 = (rb + SW_W * r1) / ITEMS, t2 = (rp[r1 + 1] + SW_W * r1) / ITEMS;
+                if (last_wave(&tk[t2], (uint32_t)(t2 - t1 + 1))) {
+                    const double tot = split_total(head, tail, t1, t2, lane);
+                    if (lane == 0) fin(r1, tot);
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
 }  // namespace lz

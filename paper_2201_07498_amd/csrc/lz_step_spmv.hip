@@ -37,8 +37,9 @@ template <> struct Epi<true> { using T = float; };
 // point so that entry e of the matrix is col_a[e] for the slab's entries,
 // launch `slab` writes its alpha partials after those of the earlier slabs,
 // and the last launch reduces all of them.  A device-resident matrix is one
-// slab of all tiles.
-template <int P, int NW, bool XCACHE, bool F = false, bool OFF32 = false>
+// slab of all tiles.  With SWEEP the relabelled matrix is walked in its
+// sweep blocks (sw) instead of tiles.
+template <int P, int NW, bool XCACHE, bool F = false, bool OFF32 = false, bool SWEEP = false>
 __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename Tr<P>::V* __restrict__ Vb,
                                                        typename Tr<P>::W* __restrict__ w, int64_t n, int64_t nnz,
                                                        int64_t ld, int64_t n_tiles, const int32_t* __restrict__ ob,
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
                                                        const int64_t* rp_a, const int32_t* col_a, const void* val_a,
                                                        const int64_t* rp_b, const int32_t* col_b, const void* val_b,
                                                        int64_t tb, int64_t te, int slab, int nslab,
-                                                       int gate) {
+                                                       int gate, SweepArgs sw) {
     using VT = typename Tr<P>::V;
     using AT = typename Tr<P>::A;
     using WT = typename Tr<P>::W;
@@ -103,13 +104,17 @@ __global__ __launch_bounds__(NW * 64) void k_spmv_step(State* st, const typename
         __syncthreads();
     }
     const int packing = rl ? st->packed : PACK_NONE;
-    if (packing == PACK_GROUP)
+    if constexpr (SWEEP) {
+        if (packing != PACK_SWEEP) return;
+        spmv_sweep<VT, NW, SweepShape<P>::ROWS>(sw, rp, x, n, tk, head, tail, pre, row, piece, fin);
+    } else if (packing == PACK_GROUP) {
         spmv_groups<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, ob, tk, head, tail, pre,
                                                row, piece, fin);
-    else
+    } else {
         spmv_tiles<VT, AT, NW, XCACHE, OFF32>(rp, col, val, x, xs, hn, n, nnz, n_tiles, tb, te,
                                               packing == PACK_TILE ? PACK_SLOTBITS : 0, ob, tk, head, tail, pre,
                                               row, piece, fin);
+    }
     if (!need_alpha) return;
     apart = block_sum(apart, shd, NW);
     if (threadIdx.x == 0) st_dev(&part[(int64_t)slab * gridDim.x + blockIdx.x], (double)apart);
@@ -154,20 +159,30 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
     using WT = typename Tr<P>::W;
     // 32-bit byte offsets reach every entry of x.
     const bool off32 = (uint64_t)p.n * sizeof(VT) <= (uint64_t(1) << 32);
+    if (p.sweep) {
+        // Relabelled matrix: its sweep blocks; the caller's order takes the
+        // tiles below (the x-head variant is not used with sweep blocks).
+        using SS = SweepShape<P>;
+        hipLaunchKernelGGL((k_spmv_step<P, SS::WAVES, false, F, false, true>), dim3(SS::GRID), dim3(SS::WAVES * 64),
+                           0, s, b.st,
+                           (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
+                           b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1, 1,
+                           SweepArgs{b.swob, b.swe, b.swcol, b.swrl, b.swval, p.sw_nb});
+    }
     if constexpr (P != 0) {
-        if (p.xcache) {
+        if (p.xcache && !p.sweep) {
             // One workgroup of XW wavefronts per CU (its LDS holds the x head).
             const int64_t g = std::min<int64_t>(256, (p.n_tiles + XW - 1) / XW);
             const int gx = (int)((g + 7) / 8 * 8);
             hipLaunchKernelGGL((k_spmv_step<P, XW, true, F>), dim3(gx), dim3(XW * 64), 0, s, b.st, (const VT*)b.V,
                                (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail, b.part2, a.rowptr,
                                a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1,
-                               p.xcache == XC_GATED ? 1 : -1);
+                               p.xcache == XC_GATED ? 1 : -1, SweepArgs{});
             if (p.xcache == XC_ON) return;
         }
     }
     {
-        const int gate = p.xcache == XC_GATED ? 0 : -1;
+        const int gate = (p.xcache == XC_GATED || p.sweep) ? 0 : -1;
         // FP32/BF16 storage: one resident set of workgroups (5 wavefronts per
         // SIMD, 256 CUs), each walking its share, so no late workgroups form
         // a tail (R-MAT 20 FP32: 80.1 -> 76.7 us).  FP64 does better the
@@ -179,12 +194,12 @@ static void spmv_step_p(const Plan& p, const Bufs& b, const Csr& a, hipStream_t 
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(g), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
                                b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1,
-                               gate);
+                               gate, SweepArgs{});
         else
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, false>), dim3(g), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
                                b.part2, a.rowptr, a.col, a.val, b.rp2, b.col2, b.val2, (int64_t)0, p.n_tiles, 0, 1,
-                               gate);
+                               gate, SweepArgs{});
     }
 }
 
@@ -198,11 +213,13 @@ static hipError_t spmv_step_ooc(const Plan& p, const Bufs& b, const Csr& a, hipS
         if (off32)
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, true>), dim3(p.g_slab), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns, -1);
+                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns, -1,
+                               SweepArgs{});
         else
             hipLaunchKernelGGL((k_spmv_step<P, WAVES, false, F, false>), dim3(p.g_slab), dim3(BLOCK), 0, s, b.st,
                                (const VT*)b.V, (WT*)b.w, a.n, a.nnz, p.ld, p.n_tiles, b.ob, b.tk, b.head, b.tail,
-                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns, -1);
+                               b.part2, a.rowptr, col, val, nullptr, nullptr, nullptr, tb, te, k, ns, -1,
+                               SweepArgs{});
     });
 }
 

@@ -41,12 +41,13 @@ def test_status_strings_and_defaults():
     assert opt.reorth == 2 and opt.report == 1 and opt.seed == 0 and not opt.workspace
     assert opt.reorder == lz.REORDER["auto"]
     assert opt.arith == lz.ARITH["mixed"]
+    assert opt.sweep == -1
 
 
 # The solve below is FP64, so the all-FP32 arithmetic (FP32 storage only) is
 # rejected as well as out-of-range values.
 @pytest.mark.parametrize("field,value", [("reorder", 3), ("reorder", -1), ("reorth", 4), ("arith", 2),
-                                         ("arith", -1), ("arith", 1)])
+                                         ("arith", -1), ("arith", 1), ("sweep", 2), ("sweep", -2)])
 def test_invalid_options_rejected_without_gpu(field, value):
     L = lz.lib()
     d = ctypes.c_void_p(16)
@@ -82,6 +83,35 @@ def test_workspace_size_grows_with_shape():
     c = lz.workspace_size(20000, 200000, 8, 24, "fp64")
     assert a > 10000 * 25 * 8 and b < a and c > a
     assert lz.workspace_size(0, 1, 1, 1, "fp64") == 0
+
+
+def test_workspace_size_of_the_sweep_blocks():
+    # Opted in below the automatic size: columns, rows within the block,
+    # values and the sort positions per entry (10 + 4 bytes in FP32), the
+    # sort's scratch and the block table on top of the default.
+    n, nnz = 100000, 1000000
+    base = lz.workspace_size(n, nnz, 8, 24, "fp32")
+    assert lz.workspace_size(n, nnz, 8, 24, "fp32", sweep="auto") == base
+    assert lz.workspace_size(n, nnz, 8, 24, "fp32", sweep="off") == base
+    on = lz.workspace_size(n, nnz, 8, 24, "fp32", sweep="on")
+    assert on >= base + nnz * (10 + 4 + 8)
+    # No relabelling, no sweep blocks.
+    assert lz.workspace_size(n, nnz, 8, 24, "fp32", sweep="on", reorder="off") == base
+    # FP64 values take 4 more bytes per entry (its blocks are twice as long,
+    # so its block table is shorter).
+    on64 = lz.workspace_size(n, nnz, 8, 24, "fp64", sweep="on")
+    assert on64 - lz.workspace_size(n, nnz, 8, 24, "fp64") >= on - base + 4 * nnz - 4096
+    # Invalid options: size 0.
+    opt = lz.Options()
+    lz.lib().lz_options_init(ctypes.byref(opt))
+    opt.sweep = 3
+    assert lz.lib().lanczos_topk_workspace_size_opt(n, nnz, 8, 24, 1, ctypes.byref(opt)) == 0
+    # The automatic choice: x of at least 64 MiB (FP32: n >= 2^24).
+    big = 1 << 24
+    assert (lz.workspace_size(big, 16 * big, 8, 32, "fp32")
+            >= lz.workspace_size(big, 16 * big, 8, 32, "fp32", sweep="off") + 16 * big * 14)
+    assert (lz.workspace_size(big // 2, 16 * big, 8, 32, "fp32")
+            == lz.workspace_size(big // 2, 16 * big, 8, 32, "fp32", sweep="off"))
 
 
 def _host_rowptr(n, nnz):

@@ -35,17 +35,25 @@ CASES = {
     # device's row-order decision picks one (R-MAT: relabelled; ER: not).
     "rmat20_bf16": (lambda: synth.rmat(20, 2, seed=4), "bf16", 4, 12),
     "er20_bf16": (lambda: synth.er(1 << 20, 5.0, seed=4), "bf16", 4, 12),
+    # Sweep blocks (opted in; 20 blocks in FP64, 40 in FP32 and BF16, rows
+    # split at their edges):
+    # the row sums are LDS atomics in one wavefront's fixed order, so two
+    # solves agree bit for bit.
+    "rmat16_fp32_sweep": (lambda: synth.rmat(16, 8, seed=3), "fp32", 8, 24, dict(sweep="on", reorder="hubs")),
+    "rmat16_fp64_sweep": (lambda: synth.rmat(16, 8, seed=3), "fp64", 8, 24, dict(sweep="on", reorder="hubs")),
+    "rmat16_bf16_sweep": (lambda: synth.rmat(16, 8, seed=3), "bf16", 8, 24, dict(sweep="on", reorder="hubs")),
 }
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_async_matches_blocking_bitwise(name):
-    gen, prec, K, m = CASES[name]
+    gen, prec, K, m = CASES[name][:4]
+    kw = CASES[name][4] if len(CASES[name]) > 4 else {}
     rp, c, v = gen()
     print(f"async {name} n={rp.size - 1} nnz={c.size}", flush=True)
     drp, dc, dv = device_csr(rp, c, v, prec)
-    a_vals, a_vecs, a_rep = lz.topk(drp, dc, dv, K, m, prec, seed=7)
-    b_vals, b_vecs, d_rep = lz.topk_async(drp, dc, dv, K, m, prec, seed=7)
+    a_vals, a_vecs, a_rep = lz.topk(drp, dc, dv, K, m, prec, seed=7, **kw)
+    b_vals, b_vecs, d_rep = lz.topk_async(drp, dc, dv, K, m, prec, seed=7, **kw)
     torch.cuda.synchronize()
     b_rep = lz.report_from_device(d_rep, K, m)
     assert torch.equal(a_vals, b_vals) and torch.equal(a_vecs, b_vecs)
@@ -55,17 +63,25 @@ def test_async_matches_blocking_bitwise(name):
         assert b_rep["spmv_layout"] == 3 | 16          # group-sorted, x head in LDS
     if name == "er20_bf16":
         assert b_rep["spmv_layout"] == 0
+    if name.endswith("_sweep"):
+        assert b_rep["spmv_layout"] == 4
+        # A second blocking solve repeats the first exactly.
+        c_vals, c_vecs, _ = lz.topk(drp, dc, dv, K, m, prec, seed=7, **kw)
+        assert torch.equal(a_vals, c_vals) and torch.equal(a_vecs, c_vecs)
 
 
-def test_async_restart_budget():
+@pytest.mark.parametrize("sweep", [None, "on"])
+def test_async_restart_budget(sweep):
     # K_12 (eigenvalues 11 and -1 x 11): the Krylov space of the start vector
-    # has dimension 2, so m = 12 steps take 10 restarts.
+    # has dimension 2, so m = 12 steps take 10 restarts.  With sweep blocks
+    # (relabelled, one block) the restart draws come from that SpMV kernel.
     rp, c, v = synth.complete(12)
     K = m = 12
+    kw = {} if sweep is None else dict(sweep=sweep, reorder="hubs")
     ref = oracle.topk(rp, c, v, K, m, seed=3)
     drp, dc, dv = device_csr(rp, c, v, "fp64")
-    a_vals, a_vecs, a_rep = lz.topk(drp, dc, dv, K, m, "fp64", seed=3)
-    b_vals, b_vecs, d_rep = lz.topk_async(drp, dc, dv, K, m, "fp64", seed=3)
+    a_vals, a_vecs, a_rep = lz.topk(drp, dc, dv, K, m, "fp64", seed=3, **kw)
+    b_vals, b_vecs, d_rep = lz.topk_async(drp, dc, dv, K, m, "fp64", seed=3, **kw)
     torch.cuda.synchronize()
     b_rep = lz.report_from_device(d_rep, K, m)
     assert a_rep["restarts"] == b_rep["restarts"] == ref["restarts"] >= 8
@@ -73,7 +89,9 @@ def test_async_restart_budget():
     same_report(a_rep, b_rep)
     # A budget below the restarts needed: the report says so and the solve
     # stops before the finish.
-    _, _, d2 = lz.topk_async(drp, dc, dv, K, m, "fp64", seed=3, max_restarts=ref["restarts"] - 1)
+    if sweep:
+        assert b_rep["spmv_layout"] == 4
+    _, _, d2 = lz.topk_async(drp, dc, dv, K, m, "fp64", seed=3, max_restarts=ref["restarts"] - 1, **kw)
     torch.cuda.synchronize()
     r2 = lz.report_from_device(d2, K, m)
     assert r2["status"] == -9 and r2["m_eff"] < m
@@ -89,20 +107,25 @@ def test_async_reports_invalid_columns_in_device_report():
     assert lz.report_from_device(d_rep, 2, 8)["status"] == -1
 
 
-def test_async_in_hip_graph_replays_bitwise():
+@pytest.mark.parametrize("sweep", [None, "on"])
+def test_async_in_hip_graph_replays_bitwise(sweep):
     # The whole solve captured in one graph on a torch stream; replays, with
     # other eager solves and synchronisations between them, reproduce the
-    # eager result exactly.
+    # eager result exactly.  With sweep blocks the capture holds the
+    # segmented sort of the setup too.
     rp, c, v = synth.rmat(13, 8, seed=5)
     rp2, c2, v2 = synth.er(3000, 9.0, seed=6)
     K, m = 6, 20
     n = rp.size - 1
+    kw = {} if sweep is None else dict(sweep=sweep, reorder="hubs")
     drp, dc, dv = device_csr(rp, c, v, "fp32")
-    ws = torch.empty(lz.workspace_size(n, c.size, K, m, "fp32"), dtype=torch.uint8, device="cuda:0")
+    ws = torch.empty(lz.workspace_size(n, c.size, K, m, "fp32", **kw), dtype=torch.uint8, device="cuda:0")
     out = (torch.empty(K, dtype=torch.float64, device="cuda:0"),
            torch.empty(K, n, dtype=torch.float64, device="cuda:0"))
     d_rep = torch.empty(lz.REPORT_BYTES, dtype=torch.uint8, device="cuda:0")
-    e_vals, e_vecs, e_rep = lz.topk(drp, dc, dv, K, m, "fp32", seed=11, workspace=ws)
+    e_vals, e_vecs, e_rep = lz.topk(drp, dc, dv, K, m, "fp32", seed=11, workspace=ws, **kw)
+    if sweep:
+        assert e_rep["spmv_layout"] == 4
     e_vals, e_vecs = e_vals.clone(), e_vecs.clone()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -111,7 +134,7 @@ def test_async_in_hip_graph_replays_bitwise():
     with torch.cuda.stream(side):
         with torch.cuda.graph(g, stream=side):
             lz.topk_async(drp, dc, dv, K, m, "fp32", seed=11, workspace=ws, out=out, d_report=d_rep,
-                          stream=side)
+                          stream=side, **kw)
     torch.cuda.current_stream().wait_stream(side)
     other = device_csr(rp2, c2, v2, "fp64")
     for rep_i in range(3):

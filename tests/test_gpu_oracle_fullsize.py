@@ -6,6 +6,10 @@ Paths (lz_report.spmv_layout names the one a solve used):
     FP32 storage selects the SpMV variant that stages the head of x in LDS.
   * R-MAT scale 21, edge factor 4 (2^20 < n < 2^22): tile-sorted storage, in
     FP64, FP32 and (with the x head in LDS) BF16.
+  * sweep blocks (each block's entries in column order, row sums in LDS):
+    the automatic choice for R-MAT scale 26 in FP32 and scale 23 in FP64,
+    opted into at R-MAT 22 and 21 (all precisions) and on a matrix whose hub
+    rows span several blocks.
   * R-MAT scale 23, edge factor 16, K = 24, m = 64 (the BF16 workload) and
     R-MAT scale 26, edge factor 16, K = 8, m = 32 (the FP32 roofline
     workload): the oracle takes minutes per solve there, so its values come
@@ -49,7 +53,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 import paper_2201_07498_amd as lz  # noqa: E402
 
-ROWS, RELABELLED, TILE_SORTED, GROUP_SORTED, XCACHE = 0, 1, 2, 3, 16
+ROWS, RELABELLED, TILE_SORTED, GROUP_SORTED, SWEEP, XCACHE = 0, 1, 2, 3, 4, 16
 U = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
 EIG_TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16": 1e-3}
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -167,6 +171,76 @@ def test_rmat22_relabelled_row_order_matches_oracle(rmat22, rmat22_ref, precisio
     check_against(f"rmat22 {precision}", precision, got, rmat22_ref, rmat22)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rmat22_sweep_blocks_match_oracle(rmat22, rmat22_ref, precision):
+    # The same matrix in sweep blocks (opted in; automatic only for larger x).
+    rp, c, v = rmat22
+    print(f"rmat22 sweep n={rp.size - 1} nnz={c.size} {precision}", flush=True)
+    got = solve(rp, c, v, 8, 24, precision, sweep="on")
+    rep = got[2]
+    assert rep["reordered"] and rep["spmv_layout"] == SWEEP, rep["spmv_layout"]
+    assert rep["restarts"] == rmat22_ref["restarts"] == 0
+    check_against(f"rmat22 sweep {precision}", precision, got, rmat22_ref, rmat22)
+
+
+def hub_matrix(n=1 << 20, hubs=(600_000, 300_000, 280_000), seed=9):
+    """An Erdos-Renyi background (about 6 off-diagonal entries per row and a
+    full diagonal) plus hub rows 0, 1, 2 joined to 600 000, 300 000 and
+    280 000 random other rows, so that after the hub-first relabelling the
+    first row spans three sweep blocks in FP64 (2^18 items each; the first two
+    own no row) and five in FP32 (2^17 items), the next two at least two
+    each.  Symmetric;
+    weights of the hub edges uniform in [0.5, 1.5); rounded to BF16 so every
+    storage precision sees the same matrix."""
+    rp, c, v = synth.er(n, 6.0, seed=seed)
+    rng = np.random.default_rng(seed)
+    R = [np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))]
+    C = [c.astype(np.int64)]
+    V = [v]
+    for h, deg in enumerate(hubs):
+        nb = rng.choice(np.arange(len(hubs), n), size=deg, replace=False)
+        w = rng.uniform(0.5, 1.5, deg)
+        R += [np.full(deg, h, np.int64), nb]
+        C += [nb, np.full(deg, h, np.int64)]
+        V += [w, w]
+    R, C, V = np.concatenate(R), np.concatenate(C), np.concatenate(V)
+    key = R * n + C
+    uk, inv = np.unique(key, return_inverse=True)
+    vals = np.zeros(uk.size)
+    np.add.at(vals, inv, V)
+    rows, cols = uk // n, uk % n
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    return np.cumsum(rowptr), cols.astype(np.int32), synth.round_values(vals, "bf16")
+
+
+@pytest.fixture(scope="module")
+def hubs():
+    return hub_matrix()
+
+
+@pytest.fixture(scope="module")
+def hubs_ref(hubs):
+    return oracle.topk(*hubs, 4, 16, seed=0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sweep_rows_across_blocks_match_oracle(hubs, hubs_ref, precision):
+    # Rows longer than a sweep block: blocks that own no row, rows in three
+    # pieces, each finished by the last piece to arrive.
+    rp, c, v = hubs
+    deg = np.diff(rp)
+    assert np.sort(deg)[-1] > 2 * (1 << 18) and np.sort(deg)[-3] > (1 << 18)
+    print(f"hubs n={rp.size - 1} nnz={c.size} {precision}", flush=True)
+    got = solve(rp, c, v, 4, 16, precision, sweep="on", reorder="hubs")
+    assert got[2]["spmv_layout"] == SWEEP
+    check_against(f"hubs sweep {precision}", precision, got, hubs_ref, hubs)
+    # The same solve on the layout this size takes without them (n = 2^20).
+    tiles = solve(rp, c, v, 4, 16, precision, sweep="off", reorder="hubs")
+    assert tiles[2]["spmv_layout"] == GROUP_SORTED
+    check_against(f"hubs group-sorted {precision}", precision, tiles, hubs_ref, hubs)
+
+
 # ------------------------------------------------------------ R-MAT 21
 @pytest.fixture(scope="module")
 def rmat21():
@@ -205,6 +279,22 @@ def test_rmat21_tile_sorted_matches_oracle(rmat21, rmat21_ref, precision):
         check_against(f"rmat21 {precision}", precision, got, ref, rmat21)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_rmat21_sweep_blocks_match_oracle(rmat21, rmat21_ref, precision):
+    # The same matrix in sweep blocks (opted in), all three storage modes.
+    rp, c, v = rmat21
+    got = solve(rp, c, v, 4, 16, precision, sweep="on")
+    assert got[2]["reordered"] and got[2]["spmv_layout"] == SWEEP, got[2]["spmv_layout"]
+    ref = rmat21_ref
+    if precision == "bf16":
+        G = golden("rmat21")
+        bound, conv, emul = bf16_bounds(ref, G["emul_bf16"]["vals"], got[2]["abs_resid"])
+        print(f"rmat21 sweep bf16: emulated err {fmt(emul)}, converged {conv}")
+        check_against("rmat21 sweep bf16", "bf16", got, ref, rmat21, eig_bound=bound)
+    else:
+        check_against(f"rmat21 sweep {precision}", precision, got, ref, rmat21)
+
+
 def test_rmat20_bf16_matches_oracle_on_attainable_pairs():
     # R-MAT 20 (group-sorted storage, head of x in LDS) in BF16 against the
     # FP64 oracle on the same BF16-rounded matrix, with the emulation bound.
@@ -238,7 +328,8 @@ def test_rmat23_matches_oracle_golden(rmat23, precision):
     got = solve(rp, c, v, 24, 64, precision, ws)
     del ws
     rep = got[2]
-    assert rep["reordered"] and rep["spmv_layout"] == RELABELLED | (XCACHE if precision == "bf16" else 0)
+    # FP64: x takes 64 MiB, so sweep blocks; BF16: rows with the x head in LDS.
+    assert rep["reordered"] and rep["spmv_layout"] == (RELABELLED | XCACHE if precision == "bf16" else SWEEP)
     assert rep["restarts"] == G["fp64"]["restarts"] == 0
     ref = G["fp64"]
     if precision == "fp64":
@@ -253,19 +344,27 @@ def test_rmat23_matches_oracle_golden(rmat23, precision):
         check_against("rmat23 bf16", "bf16", got, ref, rmat23, rows=G["sample_rows"], eig_bound=bound)
 
 
-def test_rmat26_fp32_matches_oracle_golden():
-    # R-MAT 26 (2.1 billion non-zeros, int64 row pointers), K = 8, m = 32, FP32
-    # storage: the roofline workload against the oracle's stored solve.
-    G = golden("rmat26")
+@pytest.fixture(scope="module")
+def rmat26():
     rp, c, v = synth.rmat(26, 16, seed=0)
-    v = synth.round_values(v, "fp32")
+    return rp, c, synth.round_values(v, "fp32")
+
+
+@pytest.mark.parametrize("sweep", ["auto", "off"])
+def test_rmat26_fp32_matches_oracle_golden(rmat26, sweep):
+    # R-MAT 26 (2.1 billion non-zeros, int64 row pointers), K = 8, m = 32, FP32
+    # storage: the roofline workload against the oracle's stored solve, in
+    # sweep blocks (the automatic choice at this size) and in row order with
+    # the head of x in LDS.
+    G = golden("rmat26")
+    rp, c, v = rmat26
     assert rp.size - 1 == G["n"] and c.size == G["nnz"]
     n, nnz = G["n"], G["nnz"]
-    print(f"rmat26 n={n} nnz={nnz}", flush=True)
-    ws = torch.empty(lz.workspace_size(n, nnz, 8, 32, "fp32"), dtype=torch.uint8, device="cuda:0")
-    got = solve(rp, c, v, 8, 32, "fp32", ws)
+    print(f"rmat26 n={n} nnz={nnz} sweep={sweep}", flush=True)
+    ws = torch.empty(lz.workspace_size(n, nnz, 8, 32, "fp32", sweep=sweep), dtype=torch.uint8, device="cuda:0")
+    got = solve(rp, c, v, 8, 32, "fp32", ws, sweep=sweep)
     del ws
     rep = got[2]
-    assert rep["reordered"] and rep["spmv_layout"] & 15 == RELABELLED
+    assert rep["reordered"] and rep["spmv_layout"] == (SWEEP if sweep == "auto" else RELABELLED | XCACHE)
     assert rep["restarts"] == G["fp64"]["restarts"] == 0
-    check_against("rmat26 fp32", "fp32", got, G["fp64"], (rp, c, v), rows=G["sample_rows"])
+    check_against(f"rmat26 fp32 sweep={sweep}", "fp32", got, G["fp64"], (rp, c, v), rows=G["sample_rows"])
