@@ -130,10 +130,11 @@ def spmv_bytes(n: int, nnz: int, precision: str) -> int:
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 of the sources of the Lanczos-step SpMV kernel."""
+    """SHA-256 of the sources of the Lanczos-step SpMV kernel and of the
+    layout it reads."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("lz_spmv.h", "lz_step_spmv.hip", "lz_device.h", "lz_internal.h"):
+    for f in ("lz_spmv.h", "lz_step_spmv.hip", "lz_device.h", "lz_internal.h", "lz_sweep.hip"):
         with open(os.path.join(ROOT, "paper_2201_07498_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
