@@ -410,7 +410,11 @@ struct SweepArgs {
     const void* val;
     int64_t nb;
 };
-constexpr int SW_U = 8;        // entries per lane in flight
+// Entries per lane in flight.  R-MAT 26 step SpMV with 8 / 12 / 16: FP64
+// 14.32 / 13.77 / 13.78 ms, FP32 12.49 / 12.40 / 12.45, BF16 9.66 / 9.58 /
+// 9.67 (the LDS of the row sums already limits occupancy to two wavefronts
+// per SIMD, so the extra registers cost nothing).
+constexpr int SW_U = 12;
 // Rows per block, wavefronts per workgroup (their row sums fill the LDS, so
 // one workgroup per CU) and grid, per storage precision.  Measured on
 // MI355X, R-MAT scale 26 step SpMV (rows/wavefronts/grid): FP64 4096/4/1024

@@ -16,13 +16,13 @@ torch = pytest.importorskip("torch")
 import paper_2201_07498_amd as lz  # noqa: E402
 
 
-def _solve_both(rp, c, v, K, m, prec, seed):
+def _solve_both(rp, c, v, K, m, prec, seed, **kw):
     drp, dc, dv = device_csr(rp, c, v, prec)
     n = rp.size - 1
-    ws = torch.empty(lz.workspace_size(n, c.size, K, m, prec), dtype=torch.uint8, device="cuda:0")
+    ws = torch.empty(lz.workspace_size(n, c.size, K, m, prec, **kw), dtype=torch.uint8, device="cuda:0")
     assert ws.numel() <= lz.noalloc_max_bytes()
-    a = lz.topk_async(drp, dc, dv, K, m, prec, seed=seed, workspace=ws)
-    b = lz.topk_noalloc(drp, dc, dv, K, m, prec, seed=seed)
+    a = lz.topk_async(drp, dc, dv, K, m, prec, seed=seed, workspace=ws, **kw)
+    b = lz.topk_noalloc(drp, dc, dv, K, m, prec, seed=seed, **kw)
     torch.cuda.synchronize()
     return a, b
 
@@ -40,6 +40,19 @@ def test_noalloc_matches_async_on_two_calls_second_smaller():
             assert np.array_equal(ra[key], rb[key]), key
         for key in ("restarts", "m_eff", "ortho_loss", "ritz_ortho_loss", "mean_angle_deg", "spmv_layout"):
             assert ra[key] == rb[key], key
+
+
+def test_noalloc_matches_async_with_sweep_blocks():
+    # The sweep-block layout (opted in) puts the segmented sort's scratch in
+    # the array too; two calls, the second smaller.
+    for (rp, c, v), prec in ((synth.rmat(14, 8, seed=3), "fp32"), (synth.rmat(12, 8, seed=4), "bf16")):
+        print(f"noalloc sweep n={rp.size - 1} nnz={c.size} {prec}", flush=True)
+        a, b = _solve_both(rp, c, v, 6, 20, prec, seed=2, sweep="on", reorder="hubs")
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        ra, rb = lz.report_from_device(a[2], 6, 20), lz.report_from_device(b[2], 6, 20)
+        assert ra["status"] == rb["status"] == 0 and ra["spmv_layout"] == rb["spmv_layout"] == 4
+        for key in ("alpha", "beta", "theta", "resid", "abs_resid"):
+            assert np.array_equal(ra[key], rb[key]), key
 
 
 def test_noalloc_rejects_sizes_beyond_the_scratch_array():
