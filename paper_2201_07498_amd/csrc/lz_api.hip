@@ -87,7 +87,9 @@ Plan make_plan(int64_t n, int64_t nnz, int32_t K, int32_t m, int32_t prec, bool 
         p.off_swrl = take((size_t)nnz * 2);
         p.off_swval = take((size_t)nnz * vb);
         p.off_swsrc = take((size_t)nnz * 4);
+        p.off_swvin = take((size_t)nnz * 4);
         p.off_swtmp = take(p.sw_sort_bytes);
+        p.off_swq = take(8 * 4);
     }
     p.bytes = o;
     return p;
@@ -122,7 +124,9 @@ Bufs resolve(const Plan& p, void* base) {
     b.swrl = p.sweep ? (uint16_t*)(c + p.off_swrl) : nullptr;
     b.swval = p.sweep ? c + p.off_swval : nullptr;
     b.swsrc = p.sweep ? (uint32_t*)(c + p.off_swsrc) : nullptr;
+    b.swvin = p.sweep ? (uint32_t*)(c + p.off_swvin) : nullptr;
     b.swtmp = p.sweep ? c + p.off_swtmp : nullptr;
+    b.swq = p.sweep ? (uint32_t*)(c + p.off_swq) : nullptr;
     return b;
 }
 

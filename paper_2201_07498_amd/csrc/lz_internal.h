@@ -49,6 +49,10 @@ constexpr uint32_t GROUP_SLOTMASK = (1u << GROUP_SLOTBITS) - 1u;
 constexpr int SW_W = 64;
 constexpr int SW_ROWS_MAX = 4096;
 constexpr int sweep_rows(int prec) { return prec == 0 ? 4096 : 2048; }
+// Sort payload of an entry: (row within its block << SW_POSBITS) | position
+// within its block (at most 64 * 4096 = 2^18 entries per block).
+constexpr int SW_POSBITS = 18;
+static_assert((int64_t)SW_W * 4096 <= (int64_t(1) << SW_POSBITS) && (4096 << SW_POSBITS) > 0, "sweep payload");
 // Automatic choice: relabelled matrices whose x takes at least 64 MiB.
 // Measured on MI355X, whole solve (K = 8, m = 32) of R-MAT with edge factor
 // 16, tiles -> sweep blocks: scale 24 FP32 149 -> 135 ms, FP64 196 -> 180,
@@ -133,7 +137,7 @@ struct Plan {
     size_t off_state = 0, off_V = 0, off_w = 0, off_part = 0, off_part2 = 0, off_scan = 0, off_bsum = 0,
            off_Y = 0, off_Z = 0, off_gram = 0, off_ob = 0, off_tk = 0, off_head = 0, off_tail = 0, off_rp2 = 0,
            off_col2 = 0, off_val2 = 0, off_perm = 0, off_iperm = 0, off_gm = 0, off_swob = 0, off_swe = 0,
-           off_swcol = 0, off_swrl = 0, off_swval = 0, off_swsrc = 0, off_swtmp = 0;
+           off_swcol = 0, off_swrl = 0, off_swval = 0, off_swsrc = 0, off_swvin = 0, off_swtmp = 0, off_swq = 0;
     size_t bytes = 0;
 };
 
@@ -186,14 +190,17 @@ struct Bufs {
     double* gm;        // Gram matrix of the unit stored basis, NCMAX x NCMAX
     // Sweep-block copy (Plan.sweep): first owned row and first entry of
     // every block (nb + 1), the entries' columns, rows within the block and
-    // values in column order; the sort's source positions and scratch.
+    // values in column order; the sort's payload in row order (swvin) and in
+    // column order (swsrc), and its scratch.
     int32_t* swob;
     int64_t* swe;
     int32_t* swcol;
     uint16_t* swrl;
     void* swval;
     uint32_t* swsrc;
+    uint32_t* swvin;
     void* swtmp;
+    uint32_t* swq;     // per-XCD work counters of the sweep fill (8), zeroed by the block-table kernel
 };
 Bufs resolve(const Plan& p, void* base);
 
@@ -233,9 +240,12 @@ inline bool want_xcache(const Plan& p, bool relabelled) {
 // The relabelling decision of the setup kernels, for callers that hold the
 // row pointer on the host (same integer test as on the device).
 bool host_relabel_decision(const int64_t* rowptr_host, int64_t n, int64_t nnz, int reorder);
-// Builds the sweep-block copy from the relabelled matrix (kernels return
-// unless the device chose PACK_SWEEP; the sort then sees empty blocks).
-hipError_t launch_sweep_setup(const Plan& p, const Bufs& b, hipStream_t s);
+// The sweep-block copy of the relabelled matrix, in two parts around the
+// relabelling fill (which writes the sort payload): the block table, then the
+// segmented sort and the fill of rows and values.  Kernels return unless the
+// device chose PACK_SWEEP (the sort then sees empty blocks).
+void launch_sweep_blocks(const Plan& p, const Bufs& b, hipStream_t s);
+hipError_t launch_sweep_sort(const Plan& p, const Bufs& b, hipStream_t s);
 hipError_t launch_finish(const Plan& p, const Bufs& b, const Csr& a, double* out_vals,
                          double* out_vecs, int report, hipStream_t s);
 // Copies the state into a device-resident lz_report (stream-ordered calls).

@@ -355,7 +355,8 @@ __device__ __forceinline__ int fill_tile_gather(int64_t t, const int64_t* __rest
                                                 int64_t n, int64_t nnz, const int32_t* __restrict__ ob,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
                                                 const int64_t* __restrict__ rp2, int32_t* s, int64_t* d, int lane,
-                                                int64_t* t0_out, int32_t (&c)[TP], VT (&v)[TP]) {
+                                                int64_t* t0_out, int32_t (&c)[TP], VT (&v)[TP],
+                                                int32_t (&rows)[TP]) {
     const int64_t r_lo = ob[t], r_hi = ob[t + 1];
     const int64_t t0 = t * TILE - r_lo;
     *t0_out = t0;
@@ -377,6 +378,7 @@ __device__ __forceinline__ int fill_tile_gather(int64_t t, const int64_t* __rest
         for (int step = TILE; step > 0; step >>= 1)
             if (lo + step < nr && s[lo + step] <= k) lo += step;
         src[e] = t0 + k + d[lo];
+        rows[e] = (int32_t)(r_lo + lo);
     }
 #pragma unroll
     for (int e = 0; e < TP; ++e) {
@@ -396,12 +398,16 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
                                                             const int32_t* __restrict__ perm,
                                                             const int32_t* __restrict__ iperm,
                                                             const int64_t* __restrict__ rp2,
-                                                            int32_t* __restrict__ col2, VT* __restrict__ val2) {
+                                                            int32_t* __restrict__ col2, VT* __restrict__ val2,
+                                                            const int32_t* __restrict__ swob,
+                                                            const int64_t* __restrict__ swe, int64_t sw_items,
+                                                            uint32_t* __restrict__ swvin) {
     __shared__ int32_t srp[FILL_WAVES][TILE + 2];
     __shared__ int64_t sdel[FILL_WAVES][TILE + 1];
     if (!st->reordered) return;
     if (st->packed == PACK_GROUP) return;     // k_rl_fill_group builds it
     const bool packed = st->packed == PACK_TILE;
+    const bool sweep = st->packed == PACK_SWEEP && swvin != nullptr;
     const int lane = threadIdx.x & 63;
     int32_t* s = srp[threadIdx.x >> 6];
     int64_t* d = sdel[threadIdx.x >> 6];
@@ -409,8 +415,9 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
     for (int64_t t = tr.first; t < tr.end; t += tr.stride) {
         int32_t c[TP];
         VT v[TP];
+        int32_t rows[TP];
         int64_t t0 = 0;
-        const int cnt = fill_tile_gather(t, rp, col, val, n, nnz, ob, perm, iperm, rp2, s, d, lane, &t0, c, v);
+        const int cnt = fill_tile_gather(t, rp, col, val, n, nnz, ob, perm, iperm, rp2, s, d, lane, &t0, c, v, rows);
         if (cnt <= 0) continue;                   // row ends only: no entries to move
         if (!packed) {
 #pragma unroll
@@ -419,6 +426,19 @@ __global__ __launch_bounds__(FILL_WAVES * 64) void k_rl_fill(const State* st, co
                 if (k < cnt) {
                     col2[t0 + k] = c[e];
                     val2[t0 + k] = v[e];
+                }
+            }
+            if (sweep) {
+                // Sort payload of the sweep blocks: the entry's row within its
+                // block (high bits) and its position in the block.
+#pragma unroll
+                for (int e = 0; e < TP; ++e) {
+                    const int k = e * 64 + lane;
+                    if (k < cnt) {
+                        const int64_t pos = t0 + k, r = rows[e];
+                        const int64_t b = (pos + SW_W * r) / sw_items;
+                        swvin[pos] = ((uint32_t)(r - swob[b]) << SW_POSBITS) | (uint32_t)(pos - swe[b]);
+                    }
                 }
             }
             wave_sync();
@@ -497,8 +517,9 @@ __global__ __launch_bounds__(BLOCK) void k_rl_fill_group(const State* st, const 
         int32_t c[TP];
         VT v[TP];
         int64_t t0 = 0;
+        int32_t rows[TP];
         const int cnt = t < n_tiles ? fill_tile_gather(t, rp, col, val, n, nnz, ob, perm, iperm, rp2, s, d, lane,
-                                                       &t0, c, v)
+                                                       &t0, c, v, rows)
                                     : 0;
         __syncthreads();                          // the key and value arrays overlap every wavefront's s, d
         const int off = (int)(t0 - g0);
@@ -579,21 +600,22 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
     }
     hipLaunchKernelGGL(k_setup_tiles, dim3(g), dim3(BLOCK), 0, s, b.st, n, p.n_tiles, b.ob, b.tk);
     if (reorder != LZ_REORDER_OFF) {
+        launch_sweep_blocks(p, b, s);             // the relabelling fill writes the sort payload by block
         switch (p.prec) {
             case 0:
                 hipLaunchKernelGGL(k_rl_fill<double>, dim3(p.g_tile * (WAVES / FILL_WAVES)), dim3(FILL_WAVES * 64), 0, s, b.st, a.rowptr, a.col,
                                    (const double*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
-                                   (double*)b.val2);
+                                   (double*)b.val2, b.swob, b.swe, p.sw_items, b.swvin);
                 break;
             case 1:
                 hipLaunchKernelGGL(k_rl_fill<float>, dim3(p.g_tile * (WAVES / FILL_WAVES)), dim3(FILL_WAVES * 64), 0, s, b.st, a.rowptr, a.col,
                                    (const float*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
-                                   (float*)b.val2);
+                                   (float*)b.val2, b.swob, b.swe, p.sw_items, b.swvin);
                 break;
             default:
                 hipLaunchKernelGGL(k_rl_fill<uint16_t>, dim3(p.g_tile * (WAVES / FILL_WAVES)), dim3(FILL_WAVES * 64), 0, s, b.st, a.rowptr, a.col,
                                    (const uint16_t*)a.val, n, nnz, p.n_tiles, b.ob, b.perm, b.iperm, b.rp2, b.col2,
-                                   (uint16_t*)b.val2);
+                                   (uint16_t*)b.val2, b.swob, b.swe, p.sw_items, b.swvin);
                 break;
         }
         // Group-sorted copy (decided on the device; the kernel returns unless
@@ -617,7 +639,7 @@ hipError_t launch_setup(const Plan& p, const Bufs& b, const Csr& a, uint64_t see
                                    (uint16_t*)b.val2);
                 break;
         }
-        const hipError_t e = launch_sweep_setup(p, b, s);
+        const hipError_t e = launch_sweep_sort(p, b, s);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();
