@@ -129,18 +129,19 @@ def spmv_bytes(n: int, nnz: int, precision: str) -> int:
     return nnz * (4 + vb) + (n + 1) * 8 + n * (2 * vb + wb)
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 of the sources of the Lanczos-step SpMV kernel and of the
-    layout it reads."""
+def kernel_source_hash(sweep: bool) -> str:
+    """SHA-256 of the sources of the Lanczos-step SpMV kernel, with the
+    source that builds the sweep-block layout when the solve used it."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("lz_spmv.h", "lz_step_spmv.hip", "lz_device.h", "lz_internal.h", "lz_sweep.hip"):
+    files = ("lz_spmv.h", "lz_step_spmv.hip", "lz_device.h", "lz_internal.h") + (("lz_sweep.hip",) if sweep else ())
+    for f in files:
         with open(os.path.join(ROOT, "paper_2201_07498_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, precision: str):
+def measured_traffic(workload: str, precision: str, sweep: bool):
     """HBM bytes per SpMV launch from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration), or
     None when no summary matches this workload or the kernel sources changed
@@ -154,7 +155,7 @@ def measured_traffic(workload: str, precision: str):
             if ln.startswith("- ") and ": " in ln:
                 k, v = ln[2:].split(": ", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256") != kernel_source_hash():
+    if vals.get("source_sha256") != kernel_source_hash(sweep):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -692,7 +693,7 @@ def main():
         if p != "fp64" and "fp64" in results:
             line[p]["eig_rel_err_vs_fp64_gpu"] = eig_rel_err(r["vals"], results["fp64"]["vals"])
 
-    line["roofline"]["traffic"] = measured_traffic(args.workload, head)
+    line["roofline"]["traffic"] = measured_traffic(args.workload, head, rep["spmv_layout"] & 15 == 4)
     if "fp64" in results and head != "fp64":
         # The FP64 run is the reference of the reduced-precision mode.
         line[f"eig_rel_err_{head}_vs_fp64_gpu"] = eig_rel_err(R["vals"], results["fp64"]["vals"])
