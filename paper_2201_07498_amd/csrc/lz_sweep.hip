@@ -2,13 +2,15 @@
 // large power-law matrices): the setup kernels that cut the rows into sweep
 // blocks and store each block's entries in column order.
 //
-// Why: after the hub-first relabelling the gathers of x in row order land on
-// random lines of a vector far larger than L2, one 128-byte line per
-// gathered entry.  A wavefront that walks a block's entries in column order
-// gathers x from low to high addresses, and all wavefronts of the chip do
-// so at about the same pace, so the lines one XCD pulls in are reused by its
-// other wavefronts before they leave L2.  The row sums are then accumulated
-// in LDS (one slot per row of the block) instead of in row order.
+// Why: in row order the 64 gathers of one wavefront instruction fall on up
+// to 64 different 128-byte lines of x, and beyond L2 each line costs a
+// memory request.  A wavefront that walks a block's entries in column order
+// gathers neighbouring columns in one instruction, which share lines, above
+// all in the dense head of x where the hub-first relabelling put the most
+// gathered columns.  (Measured at R-MAT scale 26, FP32: 1.02e9 -> 6.5e8
+// read requests per SpMV at about the same L2 hit rate.)  The row sums are
+// then accumulated in LDS (one slot per row of the block) instead of in row
+// order.
 //
 // Build (all on the device, stream-ordered): the block table (first owned
 // row and first entry of every block); the relabelling fill then writes each
