@@ -393,7 +393,8 @@ class Result(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("active", ctypes.c_uint64), ("queued", ctypes.c_uint64), ("arena_bytes", ctypes.c_size_t),
-                ("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+                ("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+                ("worker_enqueue_ms", ctypes.c_double)]
 
 
 def _server_lib():

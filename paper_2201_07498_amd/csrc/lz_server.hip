@@ -167,10 +167,17 @@ struct Server {
     uint64_t next_ticket = 1;
     uint64_t submitted = 0, completed = 0, rejected = 0;
     int active = 0;
+    double enqueue_ms = 0.0;     // worker time in admit / advance (read under mu)
     std::chrono::steady_clock::time_point t0;
 
     double now_ms() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    void add_enqueue_time(std::chrono::steady_clock::time_point since) {
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - since).count();
+        std::lock_guard<std::mutex> lk(mu);
+        enqueue_ms += ms;
     }
     void run();
     bool admit(Slot& s, Req* q);
@@ -295,10 +302,12 @@ void Server::run() {
             if (s.phase == IDLE) continue;
             const hipError_t e = hipEventQuery(s.ev_phase);
             if (e == hipErrorNotReady) continue;
+            const auto t0 = std::chrono::steady_clock::now();
             if (e != hipSuccess)
                 complete(s, LZ_ERR_HIP);
             else
                 advance(s);
+            add_enqueue_time(t0);
             progressed = true;
         }
         // Admission: free slots take queued requests whose footprint fits.
@@ -324,7 +333,9 @@ void Server::run() {
             if (!pick) break;
             pick->res.slot = (int)(&s - slots.data());
             progressed = true;
+            const auto t0 = std::chrono::steady_clock::now();
             if (!admit(s, pick)) complete(s, LZ_ERR_HIP);
+            add_enqueue_time(t0);
         }
         std::unique_lock<std::mutex> lk(mu);
         if (stop && queue.empty() && active == 0) break;
@@ -445,6 +456,7 @@ int lz_server_get_stats(lz_server* srv, lz_server_stats* out) {
     out->arena_bytes = s->arena.size();
     out->arena_in_use = s->arena.in_use();
     out->arena_peak = s->arena.peak();
+    out->worker_enqueue_ms = s->enqueue_ms;
     return LZ_OK;
 }
 
