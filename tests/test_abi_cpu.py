@@ -170,6 +170,30 @@ def test_host_resident_rejects_pageable_entries():
     assert rc == -1
 
 
+def test_caller_workspace_checked_against_the_sweep_plan():
+    # A workspace sized for the default options is too small once sweep
+    # blocks are asked for; the size from workspace_size(..., sweep="on") is
+    # accepted up to the point where the call would touch the GPU.  Both
+    # checks happen before any device work (dummy device pointers).
+    L = lz.lib()
+    d = ctypes.c_void_p(16)
+    n, nnz, K, m = 100000, 1000000, 4, 12
+    opt = lz.Options()
+    L.lz_options_init(ctypes.byref(opt))
+    opt.sweep = 1
+    opt.reorder = lz.REORDER["hubs"]
+    need = lz.workspace_size(n, nnz, K, m, "fp32", sweep="on", reorder="hubs")
+    assert need > lz.workspace_size(n, nnz, K, m, "fp32")
+    opt.workspace = d
+    opt.workspace_bytes = lz.workspace_size(n, nnz, K, m, "fp32")
+    for entry in ("lanczos_topk_ex", "lanczos_topk_async"):
+        last = None if entry == "lanczos_topk_ex" else ctypes.c_void_p(0)
+        rc = getattr(L, entry)(d, d, d, n, nnz, K, m, 1, None, d, d, ctypes.byref(opt), last)
+        assert rc == -4, (entry, rc)                       # LZ_ERR_WORKSPACE_TOO_SMALL
+    opt.workspace_bytes = need - 1
+    assert L.lanczos_topk_async(d, d, d, n, nnz, K, m, 1, None, d, d, ctypes.byref(opt), None) == -4
+
+
 def test_host_workspace_excludes_the_relabelled_copy():
     n, nnz = 100000, 2000000
     for prec, vb in (("fp64", 8), ("fp32", 4), ("bf16", 2)):
