@@ -157,3 +157,23 @@ def first_step_bounds(rowptr, col, val, precision, seed=0):
     e = (2.0 * L * U_WORK[precision] + U_STORE[precision] + U_WORK[precision]) * mag
     ba = float(v1 @ e)
     return 2.0 * ba, 2.0 * (float(np.linalg.norm(e)) + ba)
+
+
+BF16_TOL = 1e-3
+
+
+def bf16_bounds(ref, emul_vals, gpu_abs_resid):
+    """Per-pair bound of a BF16-storage solve against the FP64 oracle: 1e-3
+    on the pairs the FP64 oracle has converged (relative residual <= 1e-6);
+    elsewhere the larger of four times the largest error of the oracle's
+    emulation of the BF16 mode and the two runs' residuals (each Ritz value
+    lies within its residual of an eigenvalue of the matrix), at least 1e-3.
+    Which unconverged pairs move, and how far, depends on the rounding of the
+    whole Krylov sequence (Sec. III-A found 16-bit storage unstable).
+    Returns (bounds, converged mask, emulated errors)."""
+    vals = np.asarray(ref["vals"])
+    emul_err = topk_pair_err(emul_vals, vals, 1e-3, np.asarray(ref["theta"]))
+    conv = np.asarray(ref["rel_resid"]) <= 1e-6
+    band = np.maximum(max(BF16_TOL, 4.0 * float(np.max(emul_err))),
+                      (np.asarray(ref["abs_resid"]) + np.asarray(gpu_abs_resid)) / np.abs(vals))
+    return np.where(conv, BF16_TOL, band), conv, emul_err

@@ -45,8 +45,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import (check_ritz_entries, device_csr, first_step_bounds, ritz_entry_tol, subspace_cos, top2_margin,
-                      topk_pair_err)
+from gpu_util import (bf16_bounds, check_ritz_entries, device_csr, first_step_bounds, ritz_entry_tol, subspace_cos,
+                      top2_margin, topk_pair_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -73,20 +73,6 @@ def solve(rp, c, v, K, m, precision, ws=None, **kw):
 
 def fmt(a):
     return "[" + " ".join(f"{x:.1e}" for x in np.asarray(a, np.float64)) + "]"
-
-
-def bf16_bounds(ref, emul_vals, gpu_abs_resid):
-    """Per-pair BF16 bound (module docstring): 1e-3 on the pairs the FP64
-    oracle has converged; elsewhere the larger of four times the emulated
-    run's largest error and the two runs' residuals (each Ritz value lies
-    within its residual of an eigenvalue of the matrix).  Returns (bounds,
-    converged mask, emulated errors)."""
-    vals = np.asarray(ref["vals"])
-    emul_err = topk_pair_err(emul_vals, vals, 1e-3, np.asarray(ref["theta"]))
-    conv = np.asarray(ref["rel_resid"]) <= 1e-6
-    band = np.maximum(max(EIG_TOL["bf16"], 4.0 * float(np.max(emul_err))),
-                      (np.asarray(ref["abs_resid"]) + np.asarray(gpu_abs_resid)) / np.abs(vals))
-    return np.where(conv, EIG_TOL["bf16"], band), conv, emul_err
 
 
 def check_against(tag, precision, got, ref, A, rows=None, eig_bound=None):

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import device_csr, eig_rel_err
+from gpu_util import bf16_bounds, device_csr, eig_rel_err, topk_pair_err
 
 pytestmark = pytest.mark.gpu
 
@@ -17,7 +17,7 @@ import paper_2201_07498_amd as lz  # noqa: E402
 def make_requests():
     reqs = []
     specs = [("er", 6000, 9.0, 4, 12, "fp64", 1), ("rmat", 5000, 12.0, 8, 24, "fp32", 2),
-             ("er", 20000, 7.0, 8, 24, "bf16", 3), ("rmat", 30000, 20.0, 16, 48, "fp64", 4),
+             ("rmat", 20000, 7.0, 8, 24, "bf16", 3), ("rmat", 30000, 20.0, 16, 48, "fp64", 4),
              ("er", 3000, 15.0, 4, 12, "fp32", 5), ("rmat", 12000, 6.0, 4, 12, "fp64", 6)]
     for kind, n, d, K, m, prec, seed in specs:
         if kind == "er":
@@ -69,13 +69,31 @@ def test_mix_equals_alone_bitwise(use_graphs):
 
 
 def test_results_match_oracle_in_the_mix():
+    # FP64 and FP32 against the FP64 oracle at 1e-10 / 1e-6.  BF16 in Top-K
+    # order against the FP64 oracle with the per-pair bound: 1e-3 on the pairs
+    # the oracle has converged (three of the eight here), the BF16 emulation
+    # and the residuals elsewhere; its residuals come from the same request
+    # solved alone, which the mix reproduces bit for bit.
+    alone = {i: solo(q) for i, q in enumerate(REQS) if q["prec"] == "bf16"}
     with lz.Server(1 << 30, max_slots=3) as srv:
         tickets = submit_all(srv, REQS)
-        for q, t in zip(REQS, tickets):
+        for i, (q, t) in enumerate(zip(REQS, tickets)):
             vals, vecs, res = srv.wait(t)
-            ref = oracle.topk(q["rp"], q["col"], q["val"], q["K"], q["m"], seed=q["seed"], report=False)
-            tol = {"fp64": 1e-10, "fp32": 1e-6, "bf16": 2e-2}[q["prec"]]
-            assert eig_rel_err(vals, ref["vals"]) <= tol, (q["prec"], eig_rel_err(vals, ref["vals"]))
+            if q["prec"] != "bf16":
+                ref = oracle.topk(q["rp"], q["col"], q["val"], q["K"], q["m"], seed=q["seed"], report=False)
+                tol = {"fp64": 1e-10, "fp32": 1e-6}[q["prec"]]
+                assert eig_rel_err(vals, ref["vals"]) <= tol, (q["prec"], eig_rel_err(vals, ref["vals"]))
+                continue
+            ref = oracle.topk(q["rp"], q["col"], q["val"], q["K"], q["m"], seed=q["seed"])
+            emul = oracle.topk(q["rp"], q["col"], q["val"], q["K"], q["m"], seed=q["seed"], emulate="bf16",
+                               report=False)
+            va, _, rep = alone[i]
+            assert np.array_equal(vals, va)
+            bound, conv, emul_err = bf16_bounds(ref, emul["vals"], rep["abs_resid"])
+            errs = topk_pair_err(vals, np.asarray(ref["vals"]), 1e-3, np.asarray(ref["theta"]))
+            print(f"serving bf16: errors {errs}, bounds {bound}, {conv.sum()} converged")
+            assert conv.sum() >= 3
+            assert np.all(errs <= bound), (errs, bound)
 
 
 def test_small_budget_serialises_and_rejects_oversized():
