@@ -114,9 +114,9 @@ def test_tridiagonal_jacobi_matches_oracle(m, seed):
     assert 1 <= sweeps <= 20
 
 
-def run_gpu(rp, c, v, K, m, precision="fp64", seed=0, reorth="twice"):
+def run_gpu(rp, c, v, K, m, precision="fp64", seed=0, reorth="twice", **kw):
     drp, dc, dv = device_csr(rp, c, v, precision)
-    vals, vecs, rep = lz.topk(drp, dc, dv, K, m, precision, seed=seed, reorth=reorth)
+    vals, vecs, rep = lz.topk(drp, dc, dv, K, m, precision, seed=seed, reorth=reorth, **kw)
     torch.cuda.synchronize()
     return vals.cpu().numpy(), vecs.cpu().numpy(), rep
 
@@ -240,6 +240,36 @@ def test_closed_form_spectra_with_restarts(name):
     assert np.max(np.abs(np.sort(rep["theta"]) - np.sort(lam))) <= 1e-10 * max(1, np.max(np.abs(lam)))
     assert rep["restarts"] == ref["restarts"]
     assert np.max(np.abs(np.abs(vals) - np.abs(ref["vals"]))) <= 1e-10
+
+
+@pytest.mark.parametrize("name", sorted(CLOSED))
+def test_closed_form_spectra_in_sweep_blocks(name):
+    # The same graphs relabelled and forced into sweep blocks: one block
+    # (the star's hub row first), restarts drawn by the sweep kernel.
+    (rp, c, v), lam = CLOSED[name]
+    n = rp.size - 1
+    vals, Y, rep = run_gpu(rp, c, v, n, n, "fp64", seed=3, reorder="hubs", sweep="on")
+    assert rep["spmv_layout"] == 4
+    ref = oracle.topk(rp, c, v, n, n, seed=3)
+    assert np.max(np.abs(np.sort(rep["theta"]) - np.sort(lam))) <= 1e-10 * max(1, np.max(np.abs(lam)))
+    assert rep["restarts"] == ref["restarts"]
+    assert np.max(np.abs(np.abs(vals) - np.abs(ref["vals"]))) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [2, 5, 37, 2049, 70000])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ragged_sizes_in_sweep_blocks(n, precision):
+    # Forced sweep blocks at sizes from two rows to many blocks (70 000 rows
+    # of about 10 entries: 20 blocks in FP64, 40 in FP32, rows cut at every
+    # block edge); the oracle solves the same rounded matrix.
+    rp, c, v = synth.er(n, min(9.0, max(n - 1, 0)), seed=n)
+    v = synth.round_values(v, precision)
+    m = min(n, 12)
+    K = min(m, 3)
+    vals, Y, rep = run_gpu(rp, c, v, K, m, precision, seed=2, reorder="hubs", sweep="on")
+    assert rep["spmv_layout"] == 4 and rep["m_eff"] == m
+    ref = oracle.topk(rp, c, v, K, m, seed=2)
+    assert multiset_rel_err(vals, ref["vals"]) <= EIG_TOL[precision]
 
 
 def test_deterministic_bitwise():
