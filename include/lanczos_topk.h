@@ -410,9 +410,11 @@ typedef struct lz_result {
 typedef struct lz_server_stats {
     uint64_t submitted, completed, rejected, active, queued;
     size_t arena_bytes, arena_in_use, arena_peak;
-    double worker_enqueue_ms;  /* host time the worker spent enqueueing work
-                                  (copies, graph capture and launch, finish,
-                                  completion) since the server started */
+    double worker_enqueue_ms;  /* host time the slot worker threads spent
+                                  enqueueing work (copies, graph capture and
+                                  launch, finish, completion) since the server
+                                  started, summed over the threads (so it can
+                                  exceed the wall time) */
 } lz_server_stats;
 
 /* Creates a server on `device` with an HBM arena of hbm_budget_bytes and at

@@ -1,6 +1,6 @@
 // Serving runtime: continuous batching of Top-K solves on one GPU.
 //
-// A worker thread owns the device.  Requests wait in a FIFO queue; a request
+// One worker thread per slot.  Requests wait in a FIFO queue; a request
 // is admitted when one of max_slots slots is free and its footprint (CSR,
 // solver workspace, outputs) can be carved out of a fixed HBM arena
 // (first-fit, coalescing free list), so no device allocation happens while
@@ -9,8 +9,8 @@
 // backfill until it is admitted).  Each slot has its own HIP stream; an
 // admitted request's copies and kernels are enqueued there, so requests of
 // different sizes and precisions run concurrently on the device.  The Lanczos
-// iterations of a request can be captured in a hipGraph and replayed.  The
-// worker advances each slot through a small state machine by polling events:
+// iterations of a request can be captured in a hipGraph and replayed.  A
+// slot's thread advances it through a small state machine, waiting on events:
 //   ADMIT:   H2D of the CSR, setup, start vector, m iterations, D2H of state
 //   LANCZOS: restart check (more iterations if breakdowns consumed some),
 //            then Jacobi, selection, Ritz vectors, report, D2H of results
@@ -162,12 +162,12 @@ struct Server {
     std::condition_variable cv, done_cv;
     std::deque<Req*> queue;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
-    std::thread worker;
+    std::vector<std::thread> workers;
     bool stop = false;
     uint64_t next_ticket = 1;
     uint64_t submitted = 0, completed = 0, rejected = 0;
     int active = 0;
-    double enqueue_ms = 0.0;     // worker time in admit / advance (read under mu)
+    double enqueue_ms = 0.0;     // worker threads' time in admit / advance (read under mu)
     std::chrono::steady_clock::time_point t0;
 
     double now_ms() const {
@@ -179,7 +179,8 @@ struct Server {
         std::lock_guard<std::mutex> lk(mu);
         enqueue_ms += ms;
     }
-    void run();
+    void run_slot(Slot& s);
+    Req* pick(Slot& s);
     bool admit(Slot& s, Req* q);
     void advance(Slot& s);
     void complete(Slot& s, int status);
@@ -263,6 +264,7 @@ void Server::complete(Slot& s, int status) {
     s.req = nullptr;
     s.phase = IDLE;
     done_cv.notify_all();
+    cv.notify_all();                  // the freed arena block may let a waiting request in
 }
 
 void Server::advance(Slot& s) {
@@ -294,52 +296,57 @@ void Server::advance(Slot& s) {
     if (s.phase == FINISH) complete(s, st->status);
 }
 
-void Server::run() {
+// The first queued request (within the backfill window) whose footprint
+// fits the arena, taken off the queue; null if none.  Called under mu.
+Req* Server::pick(Slot& s) {
+    const int look = std::min<int>(BACKFILL, (int)queue.size());
+    for (int i = 0; i < look; ++i) {
+        if (i > 0 && queue.front()->bypassed >= MAX_BYPASS) break;
+        Req* q = queue[i];
+        size_t off = 0;
+        if (!arena.alloc(q->lay.total, &off)) continue;
+        s.off = off;
+        for (int k = 0; k < i; ++k) queue[k]->bypassed++;
+        queue.erase(queue.begin() + i);
+        ++active;
+        return q;
+    }
+    return nullptr;
+}
+
+// One worker thread per slot: it admits a request when its slot is free,
+// sleeps on the slot's phase event (created with blocking sync) while the
+// device works, and advances the slot when the event has completed.  The
+// queue, the arena and the counters are shared under mu; every thread
+// enqueues its own slot's copies and launches, so the host-side cost of
+// capture and launch is spread over the threads.
+void Server::run_slot(Slot& s) {
     (void)hipSetDevice(device);
     for (;;) {
-        bool progressed = false;
-        for (Slot& s : slots) {
-            if (s.phase == IDLE) continue;
-            const hipError_t e = hipEventQuery(s.ev_phase);
-            if (e == hipErrorNotReady) continue;
-            const auto t0 = std::chrono::steady_clock::now();
-            if (e != hipSuccess)
-                complete(s, LZ_ERR_HIP);
-            else
-                advance(s);
-            add_enqueue_time(t0);
-            progressed = true;
-        }
-        // Admission: free slots take queued requests whose footprint fits.
-        for (Slot& s : slots) {
-            if (s.phase != IDLE) continue;
-            Req* pick = nullptr;
+        if (s.phase == IDLE) {
+            Req* q = nullptr;
             {
-                std::lock_guard<std::mutex> lk(mu);
-                const int look = std::min<int>(BACKFILL, (int)queue.size());
-                for (int i = 0; i < look; ++i) {
-                    if (i > 0 && queue.front()->bypassed >= MAX_BYPASS) break;
-                    Req* q = queue[i];
-                    size_t off = 0;
-                    if (!arena.alloc(q->lay.total, &off)) continue;
-                    s.off = off;
-                    pick = q;
-                    for (int k = 0; k < i; ++k) queue[k]->bypassed++;
-                    queue.erase(queue.begin() + i);
-                    ++active;
-                    break;
+                std::unique_lock<std::mutex> lk(mu);
+                for (;;) {
+                    q = pick(s);
+                    if (q || (stop && queue.empty())) break;
+                    cv.wait(lk);
                 }
             }
-            if (!pick) break;
-            pick->res.slot = (int)(&s - slots.data());
-            progressed = true;
+            if (!q) return;
+            q->res.slot = (int)(&s - slots.data());
             const auto t0 = std::chrono::steady_clock::now();
-            if (!admit(s, pick)) complete(s, LZ_ERR_HIP);
+            if (!admit(s, q)) complete(s, LZ_ERR_HIP);
             add_enqueue_time(t0);
+            continue;
         }
-        std::unique_lock<std::mutex> lk(mu);
-        if (stop && queue.empty() && active == 0) break;
-        if (!progressed) cv.wait_for(lk, std::chrono::microseconds(50));
+        const hipError_t e = hipEventSynchronize(s.ev_phase);
+        const auto t0 = std::chrono::steady_clock::now();
+        if (e != hipSuccess)
+            complete(s, LZ_ERR_HIP);
+        else
+            advance(s);
+        add_enqueue_time(t0);
     }
 }
 
@@ -379,14 +386,15 @@ int lz_server_create(int device, size_t hbm_budget_bytes, int32_t max_slots, int
     s->slots.resize(max_slots);
     for (Slot& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreate(&sl.ev_start) != hipSuccess || hipEventCreate(&sl.ev_phase) != hipSuccess ||
+            hipEventCreate(&sl.ev_start) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.ev_phase, hipEventBlockingSync) != hipSuccess ||
             hipHostMalloc((void**)&sl.hstate, sizeof(State), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&sl.hvals, sizeof(double) * MMAX, hipHostMallocDefault) != hipSuccess) {
             lz_server_destroy((lz_server*)s);
             return LZ_ERR_HIP;
         }
     }
-    s->worker = std::thread([s] { s->run(); });
+    for (Slot& sl : s->slots) s->workers.emplace_back([s, &sl] { s->run_slot(sl); });
     *out = (lz_server*)s;
     return LZ_OK;
 }
@@ -468,7 +476,8 @@ int lz_server_destroy(lz_server* srv) {
         s->stop = true;
     }
     s->cv.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    for (std::thread& w : s->workers)
+        if (w.joinable()) w.join();
     for (Slot& sl : s->slots) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
