@@ -419,7 +419,10 @@ typedef struct lz_server_stats {
 
 /* Creates a server on `device` with an HBM arena of hbm_budget_bytes and at
  * most max_slots requests in flight; use_graphs = 1 captures each request's
- * Lanczos iterations in a hipGraph. */
+ * Lanczos iterations in a hipGraph.  Each slot gets its own stream and its
+ * own host worker thread.  LZ_ERR_OUT_OF_MEMORY if the arena, or a worker
+ * thread, cannot be had; LZ_ERR_HIP if a stream, an event or pinned state
+ * cannot be created. */
 int lz_server_create(int device, size_t hbm_budget_bytes, int32_t max_slots, int32_t use_graphs,
                      lz_server** out);
 

@@ -24,6 +24,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -394,7 +395,15 @@ int lz_server_create(int device, size_t hbm_budget_bytes, int32_t max_slots, int
             return LZ_ERR_HIP;
         }
     }
-    for (Slot& sl : s->slots) s->workers.emplace_back([s, &sl] { s->run_slot(sl); });
+    // One thread per slot.  If the system refuses a thread, the ones already
+    // started find the queue empty and stopped, and return.
+    try {
+        s->workers.reserve(s->slots.size());
+        for (Slot& sl : s->slots) s->workers.emplace_back([s, &sl] { s->run_slot(sl); });
+    } catch (const std::exception&) {
+        lz_server_destroy((lz_server*)s);
+        return LZ_ERR_OUT_OF_MEMORY;
+    }
     *out = (lz_server*)s;
     return LZ_OK;
 }
