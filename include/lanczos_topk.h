@@ -441,7 +441,8 @@ int lz_server_wait(lz_server* s, uint64_t ticket, lz_result* res);
 
 int lz_server_get_stats(lz_server* s, lz_server_stats* out);
 
-/* Waits for every request, stops the worker and frees the arena. */
+/* Waits for every queued and running request, stops the slot worker
+ * threads and frees the arena. */
 int lz_server_destroy(lz_server* s);
 
 #ifdef __cplusplus
