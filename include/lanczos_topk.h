@@ -394,6 +394,9 @@ typedef struct lz_request {
     uint64_t seed;
     double* out_vals;        /* host double[K], written on completion */
     double* out_vecs;        /* host double[n*K] column-major, or NULL */
+    double* out_resid;       /* host double[K]: relative residual of each
+                                returned pair (Top-K order, as out_vals),
+                                written on completion; or NULL */
 } lz_request;
 
 typedef struct lz_result {

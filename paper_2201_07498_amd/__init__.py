@@ -377,7 +377,7 @@ class Request(ctypes.Structure):
     _fields_ = [("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("K", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("reorth", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("out_vals", ctypes.c_void_p), ("out_vecs", ctypes.c_void_p)]
+                ("out_vals", ctypes.c_void_p), ("out_vecs", ctypes.c_void_p), ("out_resid", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -454,20 +454,23 @@ class Server:
         n = len(rowptr) - 1
         nnz = len(col)
         vals = np.zeros(K, dtype=np.float64)
+        resid = np.zeros(K, dtype=np.float64)
         vecs = np.zeros((K, n), dtype=np.float64) if want_vectors else None
         req = Request(rowptr=_host_ptr(rowptr), col=_host_ptr(col), val=_host_ptr(val), n=n, nnz=nnz, K=K, m=m,
                       precision=_prec(precision), reorth=REORTH[reorth] if isinstance(reorth, str) else int(reorth),
                       seed=seed & (2 ** 64 - 1), out_vals=vals.ctypes.data,
-                      out_vecs=vecs.ctypes.data if vecs is not None else None)
+                      out_vecs=vecs.ctypes.data if vecs is not None else None, out_resid=resid.ctypes.data)
         t = ctypes.c_uint64(0)
         rc = _server_lib().lz_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
         if rc != 0:
             raise LanczosError(rc, "lz_server_submit")
-        self._keep[t.value] = (rowptr, col, val, vals, vecs)
+        self._keep[t.value] = (rowptr, col, val, vals, vecs, resid)
         return t.value
 
     def poll(self, ticket: int):
-        """None while running, else (vals, vecs or None, result dict)."""
+        """None while running, else (vals, vecs or None, result dict).  The
+        dict holds the lz_result fields and "resid", the relative residual of
+        each returned pair in the order of vals (zeros unless status is 0)."""
         res = Result()
         rc = _server_lib().lz_server_poll(self._h, ticket, ctypes.byref(res))
         if rc == 1:
@@ -485,6 +488,7 @@ class Server:
             raise LanczosError(rc, "lz_server_poll")
         d = res.to_dict()
         d["status"] = rc
+        d["resid"] = keep[5] if keep else None
         vals, vecs = (keep[3], keep[4]) if keep else (None, None)
         return vals, (vecs.T if vecs is not None else None), d
 

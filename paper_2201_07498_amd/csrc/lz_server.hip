@@ -250,6 +250,7 @@ void Server::complete(Slot& s, int status) {
         q->res.restarts = st->restarts;
         double rm = 0.0;
         for (int k = 0; k < q->r.K; ++k) rm = std::max(rm, st->resid[k]);
+        if (q->r.out_resid) std::memcpy(q->r.out_resid, st->resid, sizeof(double) * q->r.K);
         q->res.resid_max = rm;
         q->res.ortho_loss = st->ortho_loss;
     }

@@ -62,6 +62,7 @@ def test_mix_equals_alone_bitwise(use_graphs):
             assert np.array_equal(vecs, Ya)
             assert res["m_eff"] == q["m"]
             assert res["resid_max"] == float(np.max(rep["resid"]))
+            assert np.array_equal(res["resid"], rep["resid"])
             assert res["t_submit_ms"] <= res["t_admit_ms"] <= res["t_done_ms"] and res["device_ms"] > 0
         st = srv.stats()
         assert st["completed"] == len(REQS) and st["active"] == 0 and st["queued"] == 0
