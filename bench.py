@@ -357,6 +357,15 @@ def fp32_vs_fp64_err(r32, r64) -> dict:
             "converged_pairs": len(conv), "max_converged": float(np.max(conv)) if conv else None}
 
 
+def warm_up_serving(lz, pool_dev, reqs, precisions, budget, args, count: int = 32):
+    """Untimed: the first `count` requests in each precision through a server
+    of the timed runs' shape, so that no timed run pays first-use costs (code
+    loading, first touches of pinned and device memory)."""
+    head = reqs[:count]
+    for p in precisions:
+        run_stream(lz, pool_dev, head, np.zeros(len(head)), p, budget, args.slots, not args.no_graphs)
+
+
 def run_stream(lz, pool_dev, reqs, arrivals, force_prec, budget, slots, graphs=True):
     """Submits requests at their arrival times (seconds from start) and waits
     for all.  Returns (elapsed_s, latencies_ms, results by index)."""
@@ -400,6 +409,7 @@ def serving_saturation(args) -> dict:
     reqs = serving_requests(pool, args.serving_requests)
     burst = np.zeros(len(reqs))
     budget = int(args.budget_gb * (1 << 30))
+    warm_up_serving(lz, pool_dev, reqs, ("fp32", "fp64"), budget, args)
     out = {}
     vals = {}
     for p in ("fp32", "fp64"):
@@ -431,6 +441,7 @@ def serving_main(args):
           f"{len(reqs)} requests, prepared in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
     budget = int(args.budget_gb * (1 << 30))
     burst = np.zeros(len(reqs))
+    warm_up_serving(lz, pool_dev, reqs, ("fp64", "fp32", "bf16"), budget, args)
     runs = {}
     for name, force in (("fp64", "fp64"), ("fp32", "fp32"), ("mix", None)):
         el, lat, out, st = run_stream(lz, pool_dev, reqs, burst, force, budget, args.slots, not args.no_graphs)
