@@ -643,6 +643,7 @@ template <class T, bool ROWMAJOR>
 __global__ __launch_bounds__(BLOCK) void k_gram(const State* st, const T* __restrict__ X, int64_t ldx, int64_t n,
                                                 int which, double* __restrict__ gpart) {
     __shared__ double P[GPR][64 + 1];
+    __shared__ double s_scale[64];
     if (st->status != 0) return;
     const int c = which == 0 ? min(st->j, st->m) : st->K;
     const double* scale = which == 0 ? st->scale : st->ysc;
@@ -666,25 +667,59 @@ __global__ __launch_bounds__(BLOCK) void k_gram(const State* st, const T* __rest
     // Columns c .. 16 nb - 1 enter the MFMA tiles as zeros; only the c live
     // columns are loaded per panel.
     for (int idx = threadIdx.x; idx < GPR * (nb * 16 - c); idx += BLOCK) P[idx % GPR][c + idx / GPR] = 0.0;
-    const int64_t npanel = (n + GPR - 1) / GPR;
-    for (int64_t pn = blockIdx.x; pn < npanel; pn += gridDim.x) {
-        const int64_t r0 = pn * GPR;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < GPR * c; idx += BLOCK) {
-            int row, col;
-            if (ROWMAJOR) {
-                row = idx / c;
-                col = idx - row * c;
-            } else {
-                col = idx / GPR;
-                row = idx % GPR;
-            }
-            const int64_t r = r0 + row;
-            double v = 0.0;
-            if (r < n) v = to_d(ROWMAJOR ? X[r * ldx + col] : X[(int64_t)col * ldx + r]) * scale[col];
-            P[row][col] = v;
+    if ((int)threadIdx.x < 64) s_scale[threadIdx.x] = (int)threadIdx.x < c ? scale[threadIdx.x] : 0.0;
+    // Panel element idx (< GPR c) of thread t is idx = t + q BLOCK.  All of a
+    // thread's loads of a panel go out together into registers, and the next
+    // panel's loads are issued before the current one's products, so a panel
+    // costs one memory latency, hidden behind the matrix-core work.
+    constexpr int PER = GPR * 64 / BLOCK;
+    static_assert(PER * BLOCK == GPR * 64, "a panel of 64 columns splits evenly over the threads");
+    auto locate = [&](int idx, int& row, int& col) {
+        if (ROWMAJOR) {
+            row = idx / c;
+            col = idx - row * c;
+        } else {
+            col = idx / GPR;
+            row = idx % GPR;
         }
+    };
+    T raw[PER];
+    auto load_panel = [&](int64_t pn) {
+        const int64_t r0 = pn * GPR;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = (int)threadIdx.x + q * BLOCK;
+            T v = T(0);
+            if (idx < GPR * c) {
+                int row = 0, col = 0;
+                locate(idx, row, col);
+                const int64_t r = r0 + row;
+                if (r < n) v = ROWMAJOR ? X[r * ldx + col] : X[(int64_t)col * ldx + r];
+            }
+            raw[q] = v;
+        }
+    };
+    auto store_panel = [&](int64_t pn) {
+        const int64_t r0 = pn * GPR;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = (int)threadIdx.x + q * BLOCK;
+            if (idx < GPR * c) {
+                int row = 0, col = 0;
+                locate(idx, row, col);
+                double v = 0.0;
+                if (r0 + row < n) v = to_d(raw[q]) * s_scale[col];
+                P[row][col] = v;
+            }
+        }
+    };
+    const int64_t npanel = (n + GPR - 1) / GPR;
+    if ((int64_t)blockIdx.x < npanel) load_panel(blockIdx.x);
+    for (int64_t pn = blockIdx.x; pn < npanel; pn += gridDim.x) {
+        __syncthreads();                 // P is no longer read by the previous panel's products
+        store_panel(pn);
         __syncthreads();
+        if (pn + gridDim.x < npanel) load_panel(pn + gridDim.x);
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             if (t < np) {
