@@ -124,3 +124,44 @@ def test_invalid_requests_rejected():
         t = srv.submit(rp, c, v, 2, 6, "fp64")
         vals, _, res = srv.wait(t)
         assert res["status"] == 0 and vals.shape == (2,)
+
+
+def test_concurrent_submitters_match_alone():
+    # Three host threads share one server: each submits its requests and waits
+    # for them while the others do the same (the library's calls release the
+    # interpreter lock, so submissions, completions and the slot threads
+    # interleave).  Every result equals the solve run alone.
+    import threading
+
+    alone = [solo(q) for q in REQS]
+    budget = 3 * max(lz.request_footprint(q["rp"].size - 1, q["col"].size, q["K"], q["m"], q["prec"]) for q in REQS)
+    errors = []
+    with lz.Server(budget, max_slots=3) as srv:
+        def client(indices):
+            try:
+                for _ in range(2):
+                    tickets = [(i, srv.submit(REQS[i]["rp"], REQS[i]["col"],
+                                              synth.to_storage(REQS[i]["val"], REQS[i]["prec"]), REQS[i]["K"],
+                                              REQS[i]["m"], REQS[i]["prec"], seed=REQS[i]["seed"],
+                                              want_vectors=True)) for i in indices]
+                    for i, t in tickets:
+                        vals, vecs, res = srv.wait(t)
+                        va, Ya, rep = alone[i]
+                        assert res["status"] == 0, (i, res["status"])
+                        assert np.array_equal(vals, va), i
+                        assert np.array_equal(vecs, Ya), i
+                        assert np.array_equal(res["resid"], rep["resid"]), i
+                        srv.release(t)
+            except Exception as exc:          # reported on the main thread
+                errors.append(exc)
+
+        threads = [threading.Thread(target=client, args=(list(range(k, len(REQS), 3)),)) for k in range(3)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(timeout=120)
+        assert not any(th.is_alive() for th in threads)
+        assert not errors, errors
+        st = srv.stats()
+        assert st["completed"] == 2 * len(REQS) and st["active"] == 0 and st["queued"] == 0
+        assert st["arena_in_use"] == 0 and st["arena_peak"] <= st["arena_bytes"]
